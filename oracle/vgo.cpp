@@ -1,0 +1,299 @@
+// Voxel-grid centroid downsampling -- plain CPU oracle.
+//
+// TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+// benchmark's CPU-baseline leg may load this library.  It shares no code,
+// header, table or constant with the HIP library it checks.
+//
+// What it computes (arXiv 2102.11084, Sec. II-C):
+//   * the space around the cloud is cut into a regular grid of cubes and every
+//     point is classified into one cube (Sec. II-C; Alg. 1, the per-point
+//     subdivision lookup);
+//   * a sorted key/value table gives the points of each cube and their number
+//     (Sec. II-C, the radix-sorted subdivision table);
+//   * the filter the paper accelerates is the voxel filter of the point-cloud
+//     library used by the costmap layer (Sec. I and Sec. II-C): every occupied
+//     cube is replaced by the centroid of its points; the compacted cloud is
+//     handed back (Alg. 1, final deletion/copy-back steps).
+// The paper does not write the centroid step or any rounding rule down.  The
+// readings taken here:
+//   * the grid is anchored at the per-axis minimum of the valid points and has
+//     cubic cells of edge `leaf` (the paper normalises into [-1,1]^3 and splits
+//     2^n ways, which gives non-cubic cells on a non-cubic box);
+//   * cell coordinate k = floor(RN32(RN32(p - min) * inv)), inv = RN32(1/leaf);
+//     the paper's decision tree equals this floor on a uniform grid;
+//   * a point is valid iff x, y and z are all finite (NaN or +-Inf rejected);
+//   * at most 2^21 cells per axis, else GRID_OVERFLOW (the paper stops at 2^9);
+//   * cells are emitted in ascending key order (the paper's table is sorted);
+//   * colour is the per-channel mean rounded half up, in integers.
+//
+// Implementation style: one std::map keyed by the cell key, visited in
+// ascending original index, FP64 accumulation.  Deliberately slow and plain.
+// Build: g++ -O2 -std=c++17 -ffp-contract=off -fno-fast-math -shared -fPIC
+// (no FMA contraction, no flush-to-zero; x86-64 SSE arithmetic is IEEE
+// binary32 round-to-nearest-even per operation).
+// "parity pinned": every entry point is checked by the CPU test suite against
+// closed forms, brute force and invariants.
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <vector>
+
+namespace {
+
+// Status values (numbered like the product library's, defined independently).
+enum : int {
+  VGO_OK = 0,
+  VGO_ERR_ARG = 1,
+  VGO_ERR_LEAF = 2,
+  VGO_ERR_GRID_OVERFLOW = 3,
+};
+
+enum : int { VGO_KEY_LINEAR = 0, VGO_KEY_MORTON = 1 };
+
+// A grid of at most 2^21 cells per axis keeps the 63-bit Morton key and every
+// cell coordinate exactly representable in binary32 (the paper caps its grid
+// at 2^9 per axis; Sec. II-C).
+const float kMaxCellsPerAxis = 2097152.0f;  // 2^21
+
+struct Grid {
+  float inv;        // 1/leaf, binary32, round to nearest even
+  float mn[3];      // bounding box of the valid points
+  float mx[3];
+  uint32_t d[3];    // cells per axis
+  int64_t n_valid;
+};
+
+bool point_is_valid(float x, float y, float z) {
+  return std::isfinite(x) && std::isfinite(y) && std::isfinite(z);
+}
+
+// Leaf check and inverse: the leaf must be a finite positive number whose
+// binary32 reciprocal is finite.
+int leaf_inverse(float leaf, float* inv) {
+  if (!std::isfinite(leaf) || !(leaf > 0.0f)) return VGO_ERR_LEAF;
+  float r = 1.0f / leaf;
+  if (!std::isfinite(r)) return VGO_ERR_LEAF;
+  *inv = r;
+  return VGO_OK;
+}
+
+// One cell coordinate: floor(RN32(RN32(p - min) * inv)).
+uint32_t cell_coord(float p, float mn, float inv) {
+  float diff = p - mn;
+  float t = diff * inv;
+  return (uint32_t)std::floor(t);
+}
+
+// Bounding box, cell counts per axis, overflow check (Sec. II-C grid).
+int make_grid(const float* x, const float* y, const float* z, int64_t n, float leaf, Grid* g) {
+  int st = leaf_inverse(leaf, &g->inv);
+  if (st != VGO_OK) return st;
+  g->n_valid = 0;
+  const float* c[3] = {x, y, z};
+  for (int64_t i = 0; i < n; ++i) {
+    if (!point_is_valid(x[i], y[i], z[i])) continue;
+    for (int a = 0; a < 3; ++a) {
+      float v = c[a][i];
+      if (g->n_valid == 0) {
+        g->mn[a] = v;
+        g->mx[a] = v;
+      } else {
+        if (v < g->mn[a]) g->mn[a] = v;
+        if (v > g->mx[a]) g->mx[a] = v;
+      }
+    }
+    g->n_valid += 1;
+  }
+  if (g->n_valid == 0) {
+    for (int a = 0; a < 3; ++a) { g->mn[a] = 0.0f; g->mx[a] = 0.0f; g->d[a] = 0; }
+    return VGO_OK;
+  }
+  for (int a = 0; a < 3; ++a) {
+    float extent = g->mx[a] - g->mn[a];
+    float t = extent * g->inv;
+    if (!(t < kMaxCellsPerAxis)) return VGO_ERR_GRID_OVERFLOW;
+    g->d[a] = (uint32_t)std::floor(t) + 1u;
+  }
+  return VGO_OK;
+}
+
+// Linear key: x varies fastest, then y, then z.
+uint64_t linear_key(const uint32_t k[3], const uint32_t d[3]) {
+  return (uint64_t)k[0] + (uint64_t)d[0] * ((uint64_t)k[1] + (uint64_t)d[1] * (uint64_t)k[2]);
+}
+
+// Morton key: bit b of kx goes to bit 3b, of ky to 3b+1, of kz to 3b+2.
+uint64_t morton_key(const uint32_t k[3]) {
+  uint64_t key = 0;
+  for (int b = 0; b < 21; ++b) {
+    for (int a = 0; a < 3; ++a) {
+      uint64_t bit = (k[a] >> b) & 1u;
+      key |= bit << (3 * b + a);
+    }
+  }
+  return key;
+}
+
+uint64_t point_key(const Grid& g, float px, float py, float pz, int mode) {
+  uint32_t k[3];
+  k[0] = cell_coord(px, g.mn[0], g.inv);
+  k[1] = cell_coord(py, g.mn[1], g.inv);
+  k[2] = cell_coord(pz, g.mn[2], g.inv);
+  return mode == VGO_KEY_MORTON ? morton_key(k) : linear_key(k, g.d);
+}
+
+struct Cell {
+  uint64_t n = 0;
+  int64_t ref = -1;         // first (smallest) original index seen
+  double ref_p[3] = {0, 0, 0};
+  double sum[3] = {0, 0, 0};    // sum of p
+  double local[3] = {0, 0, 0};  // sum of (p - p_ref)
+  uint64_t rgb[3] = {0, 0, 0};
+  int64_t rank = -1;
+};
+
+}  // namespace
+
+extern "C" {
+
+// Grid of a cloud: bounding box, cells per axis, valid count, and optionally
+// every point's key (0 for invalid points) and validity flag.
+int vgo_grid(const float* x, const float* y, const float* z, int64_t n, float leaf, int key_mode,
+             float* mn3, float* mx3, uint32_t* d3, int64_t* n_valid, uint64_t* keys, uint8_t* valid) {
+  if (n < 0 || (n > 0 && (!x || !y || !z))) return VGO_ERR_ARG;
+  if (key_mode != VGO_KEY_LINEAR && key_mode != VGO_KEY_MORTON) return VGO_ERR_ARG;
+  Grid g;
+  int st = make_grid(x, y, z, n, leaf, &g);
+  if (st != VGO_OK) return st;
+  if (mn3) for (int a = 0; a < 3; ++a) mn3[a] = g.mn[a];
+  if (mx3) for (int a = 0; a < 3; ++a) mx3[a] = g.mx[a];
+  if (d3) for (int a = 0; a < 3; ++a) d3[a] = g.d[a];
+  if (n_valid) *n_valid = g.n_valid;
+  for (int64_t i = 0; i < n; ++i) {
+    bool v = point_is_valid(x[i], y[i], z[i]);
+    if (valid) valid[i] = v ? 1 : 0;
+    if (keys) keys[i] = v ? point_key(g, x[i], y[i], z[i], key_mode) : 0;
+  }
+  return VGO_OK;
+}
+
+// Voxel-grid centroid filter of one cloud.  Outputs are written for cells
+// 0..m-1 in ascending key order; every output pointer may be NULL.
+//   c{x,y,z}   FP64 centroid  sum(p)/n
+//   l{x,y,z}   FP64 local mean  sum(p - p_ref)/n, p_ref = point at ref_index
+//   rgb_out    per channel floor((sum + floor(n/2)) / n), n x 3 interleaved
+//   count, key, ref_index (smallest original index in the cell)
+//   point_cell cell of every input point, -1 for invalid points
+int vgo_downsample(const float* x, const float* y, const float* z, const uint8_t* rgb, int64_t n,
+                   float leaf, int key_mode, double* cx, double* cy, double* cz, double* lx,
+                   double* ly, double* lz, uint8_t* rgb_out, uint32_t* count, uint64_t* key,
+                   int64_t* ref_index, int32_t* point_cell, int64_t* m) {
+  if (!m) return VGO_ERR_ARG;
+  *m = 0;
+  if (n < 0 || (n > 0 && (!x || !y || !z))) return VGO_ERR_ARG;
+  if (key_mode != VGO_KEY_LINEAR && key_mode != VGO_KEY_MORTON) return VGO_ERR_ARG;
+  Grid g;
+  int st = make_grid(x, y, z, n, leaf, &g);
+  if (st != VGO_OK) return st;
+
+  std::map<uint64_t, Cell> cells;
+  std::vector<uint64_t> keys(n > 0 ? (size_t)n : 1u);
+  for (int64_t i = 0; i < n; ++i) {
+    if (point_is_valid(x[i], y[i], z[i])) {
+      double p[3] = {(double)x[i], (double)y[i], (double)z[i]};
+      uint64_t k = point_key(g, x[i], y[i], z[i], key_mode);
+      keys[i] = k;
+      Cell& c = cells[k];
+      if (c.n == 0) {
+        c.ref = i;
+        for (int a = 0; a < 3; ++a) c.ref_p[a] = p[a];
+      }
+      c.n += 1;
+      for (int a = 0; a < 3; ++a) {
+        c.sum[a] += p[a];
+        c.local[a] += p[a] - c.ref_p[a];
+        if (rgb) c.rgb[a] += rgb[3 * i + a];
+      }
+    }
+  }
+
+  int64_t r = 0;
+  for (auto& kv : cells) {
+    Cell& c = kv.second;
+    c.rank = r;
+    double nn = (double)c.n;
+    if (cx) cx[r] = c.sum[0] / nn;
+    if (cy) cy[r] = c.sum[1] / nn;
+    if (cz) cz[r] = c.sum[2] / nn;
+    if (lx) lx[r] = c.local[0] / nn;
+    if (ly) ly[r] = c.local[1] / nn;
+    if (lz) lz[r] = c.local[2] / nn;
+    if (rgb_out)
+      for (int a = 0; a < 3; ++a) rgb_out[3 * r + a] = (uint8_t)((c.rgb[a] + c.n / 2) / c.n);
+    if (count) count[r] = (uint32_t)c.n;
+    if (key) key[r] = kv.first;
+    if (ref_index) ref_index[r] = c.ref;
+    ++r;
+  }
+  if (point_cell) {
+    for (int64_t i = 0; i < n; ++i) {
+      if (point_is_valid(x[i], y[i], z[i]))
+        point_cell[i] = (int32_t)cells.find(keys[i])->second.rank;
+      else
+        point_cell[i] = -1;
+    }
+  }
+  *m = r;
+  return VGO_OK;
+}
+
+// Gradient of the centroids with respect to the input coordinates, with the
+// cell assignment held fixed: dL/dp_i = G[cell(i)] / count[cell(i)], zero for
+// points outside every cell.
+int vgo_backward(const double* gx, const double* gy, const double* gz, const uint32_t* count,
+                 int64_t m, const int32_t* point_cell, int64_t n, double* dx, double* dy,
+                 double* dz) {
+  if (n < 0 || m < 0) return VGO_ERR_ARG;
+  for (int64_t i = 0; i < n; ++i) {
+    int32_t c = point_cell[i];
+    if (c < 0 || c >= m) {
+      dx[i] = 0.0;
+      dy[i] = 0.0;
+      dz[i] = 0.0;
+    } else {
+      double nn = (double)count[c];
+      dx[i] = gx[c] / nn;
+      dy[i] = gy[c] / nn;
+      dz[i] = gz[c] / nn;
+    }
+  }
+  return VGO_OK;
+}
+
+// Centroids for a given (fixed) assignment, FP64 inputs: the function whose
+// finite differences pin the backward formula.
+int vgo_centroids_fixed(const double* x, const double* y, const double* z, int64_t n,
+                        const int32_t* point_cell, int64_t m, double* cx, double* cy, double* cz) {
+  if (n < 0 || m < 0) return VGO_ERR_ARG;
+  std::vector<double> s(3 * (size_t)m, 0.0);
+  std::vector<uint64_t> cnt((size_t)m, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    int32_t c = point_cell[i];
+    if (c < 0 || c >= m) continue;
+    s[3 * c + 0] += x[i];
+    s[3 * c + 1] += y[i];
+    s[3 * c + 2] += z[i];
+    cnt[c] += 1;
+  }
+  for (int64_t k = 0; k < m; ++k) {
+    double nn = (double)cnt[k];
+    cx[k] = cnt[k] ? s[3 * k + 0] / nn : 0.0;
+    cy[k] = cnt[k] ? s[3 * k + 1] / nn : 0.0;
+    cz[k] = cnt[k] ? s[3 * k + 2] / nn : 0.0;
+  }
+  return VGO_OK;
+}
+
+}  // extern "C"

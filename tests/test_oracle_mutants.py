@@ -1,0 +1,52 @@
+"""Plant one mistake at a time in a copy of the oracle; some pin must fail.
+
+Each mutant is a plausible slip (a wrong sign, a dropped term, a transposed
+operand or index, an off-by-one).  The copy is compiled into a temporary
+library on the CPU; the oracle's own source is never changed.
+"""
+import os
+
+import pytest
+
+import oracle
+import oracle_pins as pins
+
+MUTANTS = {
+    "diff_sign": ("float diff = p - mn;", "float diff = mn - p;"),
+    "floor_to_round": ("return (uint32_t)std::floor(t);", "return (uint32_t)std::round(t);"),
+    "dims_off_by_one": ("g->d[a] = (uint32_t)std::floor(t) + 1u;", "g->d[a] = (uint32_t)std::floor(t);"),
+    "linear_wrong_dim": ("(uint64_t)d[0] * ((uint64_t)k[1]", "(uint64_t)d[1] * ((uint64_t)k[1]"),
+    "linear_axis_swap": ("return (uint64_t)k[0] + (uint64_t)d[0] * ((uint64_t)k[1] + (uint64_t)d[1] * (uint64_t)k[2]);",
+                         "return (uint64_t)k[2] + (uint64_t)d[2] * ((uint64_t)k[1] + (uint64_t)d[1] * (uint64_t)k[0]);"),
+    "morton_axis_order": ("key |= bit << (3 * b + a);", "key |= bit << (3 * b + (2 - a));"),
+    "morton_bits_short": ("for (int b = 0; b < 21; ++b) {", "for (int b = 0; b < 20; ++b) {"),
+    "sum_transposed": ("c.sum[a] += p[a];", "c.sum[a] += p[(a + 1) % 3];"),
+    "local_sign": ("c.local[a] += p[a] - c.ref_p[a];", "c.local[a] += p[a] + c.ref_p[a];"),
+    "colour_no_half": ("(c.rgb[a] + c.n / 2) / c.n", "(c.rgb[a]) / c.n"),
+    "ref_last_seen": ("if (c.n == 0) {\n        c.ref = i;", "{\n        c.ref = i;"),
+    "validity_drops_z": ("std::isfinite(y) && std::isfinite(z)", "std::isfinite(y)"),
+    "overflow_inclusive": ("if (!(t < kMaxCellsPerAxis))", "if (!(t <= kMaxCellsPerAxis))"),
+    "backward_no_div": ("dx[i] = gx[c] / nn;", "dx[i] = gx[c];"),
+    "min_uses_max": ("if (v < g->mn[a]) g->mn[a] = v;", "if (v > g->mn[a]) g->mn[a] = v;"),
+    "leaf_not_checked": ("if (!std::isfinite(r)) return VGO_ERR_LEAF;", ""),
+    "point_cell_off": ("point_cell[i] = (int32_t)cells.find(keys[i])->second.rank;",
+                       "point_cell[i] = (int32_t)cells.find(keys[i])->second.rank + 1;"),
+    "mean_divides_n_plus_1": ("if (cx) cx[r] = c.sum[0] / nn;", "if (cx) cx[r] = c.sum[0] / (nn + 1);"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path):
+    src = open(os.path.join(os.path.dirname(oracle.__file__), "vgo.cpp")).read()
+    old, new = MUTANTS[name]
+    assert src.count(old) == 1, f"mutation anchor not unique/found: {name}"
+    mpath = tmp_path / "vgo_mutant.cpp"
+    mpath.write_text(src.replace(old, new))
+    lib = oracle.load(oracle.build(str(mpath), str(tmp_path / "libmutant.so")))
+    caught = []
+    for pin in pins.ALL_PINS:
+        try:
+            pin(lib)
+        except Exception as err:  # any failure of a pin counts as catching the mutant
+            caught.append((pin.__name__, type(err).__name__))
+    assert caught, f"mutant {name} passed every pin"
