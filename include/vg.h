@@ -1,0 +1,183 @@
+/*
+ * vg.h -- voxel-grid centroid downsampling of point clouds on MI355X (gfx950).
+ *
+ * C ABI of libvg.so.  Every call takes plain pointers and sizes; device
+ * pointers point to HIP device memory of the current device, host pointers
+ * to ordinary host memory.  Streams are passed as `void *` holding a
+ * hipStream_t (NULL = the default stream).
+ *
+ * The operation (arXiv 2102.11084, Sec. II-C and Alg. 1; the filter of
+ * Sec. I / Sec. II-C that the paper moves off the CPU):
+ *   1. a point (x, y, z) is valid iff all three coordinates are finite;
+ *   2. the grid is anchored at min_a = min over valid points of coordinate a
+ *      and has cubic cells of edge `leaf`; inv = RN32(1/leaf) is computed once
+ *      on the host;
+ *   3. cell coordinate k_a = floor(RN32(RN32(p_a - min_a) * inv)) in binary32,
+ *      cells per axis d_a = floor(RN32(RN32(max_a - min_a) * inv)) + 1, and
+ *      more than 2^21 cells on an axis is VG_ERR_GRID_OVERFLOW;
+ *   4. key = k_x + d_x * (k_y + d_y * k_z)        (VG_KEY_LINEAR), or
+ *      key = bit-interleave, bit b of k_x at 3b, k_y at 3b+1, k_z at 3b+2
+ *                                                 (VG_KEY_MORTON);
+ *   5. (key, index) pairs are sorted by key with a stable radix sort, so the
+ *      points of a cell are contiguous and in input order (the paper's sorted
+ *      subdivision table);
+ *   6. each occupied cell becomes one output row, rows in ascending key:
+ *      centroid = mean of its points' xyz, colour = per-channel
+ *      floor((sum + floor(n/2)) / n), count n, key, and the smallest input
+ *      index among its points.
+ *
+ * Errors: every call returns a vg_status and never throws.  Argument errors
+ * are detected on the host before anything is launched; on any error the
+ * output contents are unspecified and *m (where present) is 0.
+ * Ownership: the caller owns every buffer it passes; the library frees none
+ * of them.  A batch plan owns only what vg_batch_plan_create allocated.
+ * A workspace serves one call at a time: calls that share a workspace must be
+ * ordered (for example, issued on one stream).
+ */
+#ifndef VG_H
+#define VG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum vg_status {
+  VG_OK = 0,
+  VG_ERR_ARG = 1,            /* null pointer, negative or too large size, bad enum */
+  VG_ERR_LEAF = 2,           /* leaf not finite, not > 0, or 1/leaf not finite */
+  VG_ERR_GRID_OVERFLOW = 3,  /* more than 2^21 cells on some axis */
+  VG_ERR_WORKSPACE = 4,      /* workspace smaller than vg_workspace_bytes() */
+  VG_ERR_DEVICE = 5          /* HIP runtime error, or a device-side time-out */
+} vg_status;
+
+typedef enum vg_key_mode { VG_KEY_LINEAR = 0, VG_KEY_MORTON = 1 } vg_key_mode;
+
+/* How the pipeline is launched.  PERSISTENT: one kernel whose workgroups take
+ * tiles of every phase from a work queue ordered so that a tile only waits on
+ * tiles dequeued before it.  PHASED: one launch per phase (same device code),
+ * used to time each phase on its own. */
+typedef enum vg_exec_mode { VG_EXEC_PERSISTENT = 0, VG_EXEC_PHASED = 1 } vg_exec_mode;
+
+/* Input cloud, structure of arrays, device memory.  x, y, z: n binary32 each.
+ * rgb: n x 3 uint8 interleaved, or NULL (then output colours are not written). */
+typedef struct vg_points {
+  const float *x, *y, *z;
+  const uint8_t *rgb;
+} vg_points;
+
+/* Output cells, device memory, capacity >= number of input points.
+ * Every pointer may be NULL, then that output is not written.
+ *   x, y, z     centroid (binary32)
+ *   rgb         m x 3 uint8
+ *   count       points in the cell
+ *   key         64-bit cell key
+ *   point_cell  [n]: output row of every input point, -1 for invalid points
+ *               (rows of a batch are rows of the concatenated output)
+ *   ref_index   smallest input index among the cell's points (an index into
+ *               the arrays passed to the call)
+ *   lx, ly, lz  mean of (p - p_ref), p_ref = the point at ref_index */
+typedef struct vg_cells {
+  float *x, *y, *z;
+  uint8_t *rgb;
+  uint32_t *count;
+  uint64_t *key;
+  int32_t *point_cell;
+  uint32_t *ref_index;
+  float *lx, *ly, *lz;
+} vg_cells;
+
+/* Tile shapes and launch shape.  A variant must be one the library was built
+ * with (vg_tuning_supported).  radix_bits is the widest digit of a sort pass;
+ * a frame whose key has b bits is sorted in P = max(1, ceil(b / radix_bits))
+ * passes of ceil(b / P) bits. */
+typedef struct vg_tuning {
+  int sort_block;     /* threads per sort/bbox/histogram tile */
+  int sort_items;     /* items per thread of such a tile */
+  int radix_bits;     /* widest radix digit */
+  int reduce_block;   /* threads per reduce tile */
+  int reduce_items;   /* items per thread of a reduce tile */
+  int blocks_per_cu;  /* persistent grid = CUs x this (0: occupancy limit) */
+  int exec_mode;      /* vg_exec_mode */
+} vg_tuning;
+
+/* Per-call options.  workspace: device memory of at least
+ * vg_workspace_bytes(n, 1, tuning) bytes, or NULL (then the call allocates
+ * and frees its own, which costs a hipMalloc/hipFree pair).  tuning: NULL =
+ * the built-in default. */
+typedef struct vg_options {
+  void *stream;
+  void *workspace;
+  size_t workspace_bytes;
+  vg_key_mode key_mode;
+  const vg_tuning *tuning;
+} vg_options;
+
+/* Human-readable name of a status; never NULL. */
+const char *vg_status_string(vg_status s);
+
+/* Fills *t with the built-in default tuning.  VG_ERR_ARG if t is NULL. */
+vg_status vg_default_tuning(vg_tuning *t);
+
+/* VG_OK if the library holds kernels for this tuning, else VG_ERR_ARG. */
+vg_status vg_tuning_supported(const vg_tuning *t);
+
+/* Device workspace needed for n_total points in n_frames frames (0 on bad
+ * arguments).  Grows linearly in n_total (about 26 bytes per point). */
+size_t vg_workspace_bytes(int64_t n_total, int n_frames, const vg_tuning *t);
+
+/* Downsample one cloud on the default stream with an internal workspace.
+ * p: device points; n: number of points, 0 <= n < 2^30; leaf: cell edge;
+ * out: device outputs of capacity n; m: host, receives the number of cells.
+ * Synchronous: returns after the cells are written (one stream sync). */
+vg_status vg_downsample(const vg_points *p, int64_t n, float leaf, vg_cells *out, int64_t *m);
+
+/* As vg_downsample, with a stream, a caller workspace, key mode and tuning.
+ * Waits for the stream only to read m back. */
+vg_status vg_downsample_ex(const vg_points *p, int64_t n, float leaf, vg_cells *out, int64_t *m,
+                           const vg_options *o);
+
+/* Backward of the centroids with the cell assignment held fixed:
+ *   d{x,y,z}[i] = g{x,y,z}[c] / count[c] for c = point_cell[i] >= 0, else 0.
+ * g*, count: device [m]; point_cell: device [n] (as written by a forward
+ * call); d*: device [n].  Asynchronous on `stream`.  0 <= n < 2^31. */
+vg_status vg_downsample_backward(const float *gx, const float *gy, const float *gz,
+                                 const uint32_t *count, int64_t m, const int32_t *point_cell,
+                                 int64_t n, float *dx, float *dy, float *dz, void *stream);
+
+/* ---- batched form: many frames of uneven size and leaf in one launch ---- */
+typedef struct vg_batch_plan vg_batch_plan;
+
+/* Plan for up to max_frames frames and max_total_points points in total
+ * (< 2^31, and < 2^30 per frame).  Allocates the device workspace and a
+ * pinned descriptor buffer.  tuning NULL = default. */
+vg_status vg_batch_plan_create(int max_frames, int64_t max_total_points, vg_key_mode key_mode,
+                               const vg_tuning *tuning, vg_batch_plan **plan);
+
+/* If use_graph != 0, the plan records its launch sequence (descriptor copy,
+ * state reset, pipeline kernel) into a hipGraph on first use and replays it. */
+vg_status vg_batch_plan_set_graph(vg_batch_plan *plan, int use_graph);
+
+/* Downsample B frames concatenated in p.  frame_offsets: host [B+1],
+ * non-decreasing, frame b = points [frame_offsets[b], frame_offsets[b+1]).
+ * leaf: host [B].  out: device, capacity frame_offsets[B]; frame b's cells
+ * are rows [out_offsets[b], out_offsets[b+1]) of every output array.
+ * out_offsets: device int64 [B+1]; frame_status: device int32 [B]
+ * (VG_OK or VG_ERR_GRID_OVERFLOW; an overflowing frame has no rows).
+ * Fully asynchronous on `stream`; a later call on the same plan waits for
+ * the earlier one's descriptor copy before reusing the pinned buffer. */
+vg_status vg_downsample_batched(vg_batch_plan *plan, const vg_points *p,
+                                const int64_t *frame_offsets, const float *leaf, int B,
+                                vg_cells *out, int64_t *out_offsets, int32_t *frame_status,
+                                void *stream);
+
+/* Releases the plan (waits for its work to finish first). */
+vg_status vg_batch_plan_destroy(vg_batch_plan *plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VG_H */

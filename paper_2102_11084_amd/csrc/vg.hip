@@ -1,0 +1,581 @@
+// Host side of libvg: argument checks, workspace layout, launch sequence,
+// batch plans and hipGraph replay.  Device code lives in vg_pipeline.hpp.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+
+#include "../../include/vg.h"
+#include "vg_pipeline.hpp"
+
+namespace {
+
+using namespace vg;
+
+// ------------------------------------------------------------ variants ----
+struct Variant {
+  int block, sort_items, radix, red_items;
+  int nph, maxp, R, TS, TR, ph_red;
+  void (*launch)(const Ws&, int ph_lo, int ph_hi, int grid, hipStream_t);
+  int (*occupancy)();
+};
+
+template <class C>
+void launch_pipeline(const Ws& ws, int lo, int hi, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(vg_pipeline_kernel<C>, dim3(grid), dim3(C::BLOCK), 0, s, ws, lo, hi);
+}
+
+template <class C>
+int occupancy_of() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, vg_pipeline_kernel<C>, C::BLOCK, 0) !=
+      hipSuccess)
+    return 1;
+  return std::max(n, 1);
+}
+
+template <int B, int SI, int W, int RI>
+constexpr Variant make_variant() {
+  using C = Cfg<B, SI, W, RI>;
+  return Variant{B, SI, W, RI, C::NPH, C::MAXP, C::R, C::TS, C::TR, C::PH_RED,
+                 &launch_pipeline<C>, &occupancy_of<C>};
+}
+
+// Built variants: (threads, sort items/thread, radix bits, reduce items/thread).
+const Variant kVariants[] = {
+    make_variant<256, 16, 8, 8>(), make_variant<256, 8, 8, 8>(),  make_variant<256, 12, 8, 8>(),
+    make_variant<256, 16, 8, 4>(), make_variant<256, 16, 7, 8>(), make_variant<512, 8, 8, 4>(),
+    make_variant<512, 8, 8, 8>(),  make_variant<256, 16, 6, 8>(),
+};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+const vg_tuning kDefaultTuning = {256, 16, 8, 256, 8, 0, VG_EXEC_PERSISTENT};
+
+const Variant* find_variant(const vg_tuning* t) {
+  if (!t) t = &kDefaultTuning;
+  if (t->sort_block != t->reduce_block) return nullptr;
+  if (t->exec_mode != VG_EXEC_PERSISTENT && t->exec_mode != VG_EXEC_PHASED) return nullptr;
+  if (t->blocks_per_cu < 0 || t->blocks_per_cu > 64) return nullptr;
+  for (int i = 0; i < kNumVariants; ++i) {
+    const Variant& v = kVariants[i];
+    if (v.block == t->sort_block && v.sort_items == t->sort_items && v.radix == t->radix_bits &&
+        v.red_items == t->reduce_items)
+      return &v;
+  }
+  return nullptr;
+}
+
+// Per-device facts, looked up once.
+struct DeviceInfo {
+  int cus = 0;
+  int occ[kNumVariants] = {};
+};
+std::mutex g_dev_mu;
+DeviceInfo g_dev[64];
+
+bool device_info(int dev, const Variant* v, int* cus, int* occ) {
+  if (dev < 0 || dev >= 64) return false;
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  DeviceInfo& d = g_dev[dev];
+  if (d.cus == 0) {
+    int c = 0;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
+      return false;
+    d.cus = c;
+  }
+  const int vi = (int)(v - kVariants);
+  if (d.occ[vi] == 0) d.occ[vi] = v->occupancy();
+  *cus = d.cus;
+  *occ = d.occ[vi];
+  return true;
+}
+
+// ------------------------------------------------------------ layout ----
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  int64_t capN;
+  int capB, capNTs, capNTr, slots, R;
+  size_t hdr, io, fd, tps, tpr, staged;   // staged = bytes copied from the host each call
+  size_t ctl, fs, hist, sdesc, rdesc, fflag, frag, lo0, lo1, hi0, hi1, id0, id1, outoff, fstat;
+  size_t total;
+};
+
+int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+Layout make_layout(int64_t capN, int capB, const Variant& v) {
+  Layout L;
+  L.capN = std::max<int64_t>(capN, 1);
+  L.capB = std::max(capB, 1);
+  L.capNTs = (int)(div_up(L.capN, v.TS) + L.capB);
+  L.capNTr = (int)(div_up(L.capN, v.TR) + L.capB);
+  L.slots = v.maxp;
+  L.R = v.R;
+  size_t o = 0;
+  L.hdr = o;  o = align_up(o + sizeof(CallHdr));
+  L.io = o;   o = align_up(o + sizeof(Io));
+  L.fd = o;   o = align_up(o + sizeof(FrameDesc) * L.capB);
+  L.tps = o;  o = align_up(o + 4 * (size_t)(L.capB + 1));
+  L.tpr = o;  o = align_up(o + 4 * (size_t)(L.capB + 1));
+  L.staged = o;
+  L.ctl = o;  o = align_up(o + sizeof(Ctl));
+  L.fs = o;   o = align_up(o + sizeof(FrameState) * L.capB);
+  L.hist = o; o = align_up(o + 4 * (size_t)L.capB * L.slots * L.R);
+  L.sdesc = o; o = align_up(o + 4 * (size_t)L.slots * L.capNTs * L.R);
+  L.rdesc = o; o = align_up(o + 8 * (size_t)L.capNTr);
+  L.fflag = o; o = align_up(o + 4 * (size_t)L.capNTr);
+  L.frag = o; o = align_up(o + sizeof(Frag) * (size_t)L.capNTr);
+  const size_t nb = 4 * (size_t)L.capN;
+  L.lo0 = o; o = align_up(o + nb);
+  L.lo1 = o; o = align_up(o + nb);
+  L.hi0 = o; o = align_up(o + nb);
+  L.hi1 = o; o = align_up(o + nb);
+  L.id0 = o; o = align_up(o + nb);
+  L.id1 = o; o = align_up(o + nb);
+  L.outoff = o; o = align_up(o + 8 * (size_t)(L.capB + 1));
+  L.fstat = o; o = align_up(o + 4 * (size_t)L.capB);
+  L.total = o;
+  return L;
+}
+
+Ws carve(const Layout& L, void* base) {
+  char* b = static_cast<char*>(base);
+  Ws w;
+  w.hdr = reinterpret_cast<CallHdr*>(b + L.hdr);
+  w.io = reinterpret_cast<Io*>(b + L.io);
+  w.fd = reinterpret_cast<FrameDesc*>(b + L.fd);
+  w.tps = reinterpret_cast<uint32_t*>(b + L.tps);
+  w.tpr = reinterpret_cast<uint32_t*>(b + L.tpr);
+  w.ctl = reinterpret_cast<Ctl*>(b + L.ctl);
+  w.fs = reinterpret_cast<FrameState*>(b + L.fs);
+  w.hist = reinterpret_cast<uint32_t*>(b + L.hist);
+  w.sdesc = reinterpret_cast<uint32_t*>(b + L.sdesc);
+  w.rdesc = reinterpret_cast<uint64_t*>(b + L.rdesc);
+  w.fflag = reinterpret_cast<uint32_t*>(b + L.fflag);
+  w.frag = reinterpret_cast<Frag*>(b + L.frag);
+  w.lo[0] = reinterpret_cast<uint32_t*>(b + L.lo0);
+  w.lo[1] = reinterpret_cast<uint32_t*>(b + L.lo1);
+  w.hi[0] = reinterpret_cast<uint32_t*>(b + L.hi0);
+  w.hi[1] = reinterpret_cast<uint32_t*>(b + L.hi1);
+  w.idx[0] = reinterpret_cast<uint32_t*>(b + L.id0);
+  w.idx[1] = reinterpret_cast<uint32_t*>(b + L.id1);
+  w.capB = L.capB;
+  w.capNTs = L.capNTs;
+  w.capNTr = L.capNTr;
+  w.slots = L.slots;
+  w.R = L.R;
+  w.capN = L.capN;
+  return w;
+}
+
+// ---------------------------------------------------------- checks ----
+bool leaf_inverse(float leaf, float* inv) {
+  if (!std::isfinite(leaf) || !(leaf > 0.0f)) return false;
+  volatile float one = 1.0f;
+  float r = one / leaf;  // binary32 division, round to nearest even
+  if (!std::isfinite(r)) return false;
+  *inv = r;
+  return true;
+}
+
+uint32_t want_mask(const vg_cells* c) {
+  uint32_t w = 0;
+  if (c->x && c->y && c->z) w |= kOutXYZ;
+  if (c->rgb) w |= kOutRGB;
+  if (c->count) w |= kOutCount;
+  if (c->key) w |= kOutKey;
+  if (c->point_cell) w |= kOutPointCell;
+  if (c->ref_index) w |= kOutRef;
+  if (c->lx && c->ly && c->lz) w |= kOutLocal;
+  return w;
+}
+
+bool cells_consistent(const vg_cells* c) {
+  // x/y/z and lx/ly/lz come as complete triples or not at all
+  const int xyz = (c->x != nullptr) + (c->y != nullptr) + (c->z != nullptr);
+  const int loc = (c->lx != nullptr) + (c->ly != nullptr) + (c->lz != nullptr);
+  return (xyz == 0 || xyz == 3) && (loc == 0 || loc == 3);
+}
+
+// Fills the staged region (header, io, frame descriptors, tile prefixes) on
+// the host.  Returns false if some frame is too large.
+bool fill_staging(char* st, const Layout& L, const Variant& v, const vg_points* p,
+                  const int64_t* offs, const float* leaves, const float* invs, int B,
+                  const vg_cells* out, int64_t* out_offsets, int32_t* frame_status, int key_mode,
+                  CallHdr* hdr_out) {
+  CallHdr hdr;
+  std::memset(&hdr, 0, sizeof hdr);
+  hdr.B = B;
+  hdr.key_mode = key_mode;
+  hdr.N = offs[B] - offs[0];
+  hdr.want = want_mask(out);
+  if (!p->rgb) hdr.want &= ~(uint32_t)kOutRGB;
+  Io io;
+  std::memset(&io, 0, sizeof io);
+  io.x = p->x;
+  io.y = p->y;
+  io.z = p->z;
+  io.rgb = p->rgb;
+  io.cx = out->x;
+  io.cy = out->y;
+  io.cz = out->z;
+  io.crgb = out->rgb;
+  io.count = out->count;
+  io.key = out->key;
+  io.point_cell = out->point_cell;
+  io.ref_index = out->ref_index;
+  io.lx = out->lx;
+  io.ly = out->ly;
+  io.lz = out->lz;
+  io.out_offsets = out_offsets;
+  io.frame_status = frame_status;
+  FrameDesc* fd = reinterpret_cast<FrameDesc*>(st + L.fd);
+  uint32_t* tps = reinterpret_cast<uint32_t*>(st + L.tps);
+  uint32_t* tpr = reinterpret_cast<uint32_t*>(st + L.tpr);
+  int64_t ts = 0, tr = 0;
+  for (int b = 0; b < B; ++b) {
+    const int64_t n = offs[b + 1] - offs[b];
+    if (n < 0 || n > kMaxFramePoints) return false;
+    fd[b].off = offs[b] - offs[0];
+    fd[b].n = n;
+    fd[b].leaf = leaves[b];
+    fd[b].inv = invs[b];
+    fd[b].pad = 0;
+    tps[b] = (uint32_t)ts;
+    tpr[b] = (uint32_t)tr;
+    ts += std::max<int64_t>(1, div_up(n, v.TS));
+    tr += std::max<int64_t>(1, div_up(n, v.TR));
+  }
+  tps[B] = (uint32_t)ts;
+  tpr[B] = (uint32_t)tr;
+  if (ts > L.capNTs || tr > L.capNTr) return false;
+  hdr.NTs = (int32_t)ts;
+  hdr.NTr = (int32_t)tr;
+  std::memcpy(st + L.hdr, &hdr, sizeof hdr);
+  std::memcpy(st + L.io, &io, sizeof io);
+  *hdr_out = hdr;
+  return true;
+}
+
+// Enqueues: staged copy, state reset, pipeline.  All launches have fixed
+// shapes (no per-call kernel arguments), so the sequence can be captured.
+vg_status enqueue(const Variant& v, const Layout& L, const Ws& ws, const char* staging,
+                  int exec_mode, int grid, hipStream_t s) {
+  if (hipMemcpyAsync(ws.hdr, staging, L.staged, hipMemcpyHostToDevice, s) != hipSuccess)
+    return VG_ERR_DEVICE;
+  hipLaunchKernelGGL(vg_init_kernel, dim3(256), dim3(256), 0, s, ws);
+  if (exec_mode == VG_EXEC_PERSISTENT) {
+    v.launch(ws, 0, v.nph, grid, s);
+  } else {
+    for (int ph = 0; ph < v.nph; ++ph) v.launch(ws, ph, ph + 1, grid, s);
+  }
+  if (hipGetLastError() != hipSuccess) return VG_ERR_DEVICE;
+  return VG_OK;
+}
+
+int grid_for(const Variant& v, const vg_tuning* t, int dev) {
+  int cus = 0, occ = 1;
+  if (!device_info(dev, &v, &cus, &occ)) return -1;
+  const int bpc = (t && t->blocks_per_cu > 0) ? std::min(t->blocks_per_cu, occ) : occ;
+  return cus * bpc;
+}
+
+// Per host thread pinned staging for the synchronous single-cloud path.
+struct ThreadStaging {
+  char* buf = nullptr;
+  size_t bytes = 0;
+  ~ThreadStaging() {
+    if (buf) (void)hipHostFree(buf);
+  }
+  char* get(size_t need) {
+    if (bytes < need) {
+      if (buf) (void)hipHostFree(buf);
+      buf = nullptr;
+      bytes = 0;
+      if (hipHostMalloc(reinterpret_cast<void**>(&buf), need, hipHostMallocDefault) != hipSuccess)
+        return nullptr;
+      bytes = need;
+    }
+    return buf;
+  }
+};
+thread_local ThreadStaging t_staging;
+
+struct Readback {
+  int64_t off[2];
+  int32_t status;
+  uint32_t error;
+};
+
+}  // namespace
+
+// ================================================================ C ABI ====
+extern "C" {
+
+const char* vg_status_string(vg_status s) {
+  switch (s) {
+    case VG_OK: return "VG_OK";
+    case VG_ERR_ARG: return "VG_ERR_ARG: invalid argument";
+    case VG_ERR_LEAF: return "VG_ERR_LEAF: leaf must be finite and > 0 with a finite reciprocal";
+    case VG_ERR_GRID_OVERFLOW: return "VG_ERR_GRID_OVERFLOW: more than 2^21 cells on an axis";
+    case VG_ERR_WORKSPACE: return "VG_ERR_WORKSPACE: workspace too small";
+    case VG_ERR_DEVICE: return "VG_ERR_DEVICE: HIP runtime error or device time-out";
+  }
+  return "VG_ERR_UNKNOWN";
+}
+
+vg_status vg_default_tuning(vg_tuning* t) {
+  if (!t) return VG_ERR_ARG;
+  *t = kDefaultTuning;
+  return VG_OK;
+}
+
+vg_status vg_tuning_supported(const vg_tuning* t) {
+  return (t && find_variant(t)) ? VG_OK : VG_ERR_ARG;
+}
+
+size_t vg_workspace_bytes(int64_t n_total, int n_frames, const vg_tuning* t) {
+  const Variant* v = find_variant(t);
+  if (!v || n_total < 0 || n_total > INT32_MAX || n_frames < 1) return 0;
+  return make_layout(n_total, n_frames, *v).total;
+}
+
+vg_status vg_downsample_ex(const vg_points* p, int64_t n, float leaf, vg_cells* out, int64_t* m,
+                           const vg_options* o) {
+  if (m) *m = 0;
+  if (!p || !out || !m || !o) return VG_ERR_ARG;
+  if (n < 0 || n > kMaxFramePoints) return VG_ERR_ARG;
+  if (o->key_mode != VG_KEY_LINEAR && o->key_mode != VG_KEY_MORTON) return VG_ERR_ARG;
+  if (n > 0 && (!p->x || !p->y || !p->z)) return VG_ERR_ARG;
+  if (!cells_consistent(out)) return VG_ERR_ARG;
+  const Variant* v = find_variant(o->tuning);
+  if (!v) return VG_ERR_ARG;
+  float inv;
+  if (!leaf_inverse(leaf, &inv)) return VG_ERR_LEAF;
+  if (n == 0) return VG_OK;
+  const Layout L = make_layout(n, 1, *v);
+  if (o->workspace && o->workspace_bytes < L.total) return VG_ERR_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(o->stream);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return VG_ERR_DEVICE;
+  const int grid = grid_for(*v, o->tuning, dev);
+  if (grid <= 0) return VG_ERR_DEVICE;
+
+  char* st = t_staging.get(L.staged + sizeof(Readback));
+  if (!st) return VG_ERR_DEVICE;
+  void* base = o->workspace;
+  bool owned = false;
+  if (!base) {
+    if (hipMalloc(&base, L.total) != hipSuccess) return VG_ERR_DEVICE;
+    owned = true;
+  }
+  Ws ws = carve(L, base);
+  const int64_t offs[2] = {0, n};
+  CallHdr hdr;
+  int64_t* d_off = reinterpret_cast<int64_t*>(static_cast<char*>(base) + L.outoff);
+  int32_t* d_st = reinterpret_cast<int32_t*>(static_cast<char*>(base) + L.fstat);
+  vg_status rc = VG_OK;
+  if (!fill_staging(st, L, *v, p, offs, &leaf, &inv, 1, out, d_off, d_st, o->key_mode, &hdr)) {
+    rc = VG_ERR_ARG;
+  } else {
+    const int mode = o->tuning ? o->tuning->exec_mode : kDefaultTuning.exec_mode;
+    rc = enqueue(*v, L, ws, st, mode, grid, s);
+  }
+  Readback* rb = reinterpret_cast<Readback*>(st + L.staged);
+  if (rc == VG_OK) {
+    bool ok = hipMemcpyAsync(&rb->off[0], d_off, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s) ==
+                  hipSuccess &&
+              hipMemcpyAsync(&rb->status, d_st, sizeof(int32_t), hipMemcpyDeviceToHost, s) ==
+                  hipSuccess &&
+              hipMemcpyAsync(&rb->error, &ws.ctl->error, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                             s) == hipSuccess &&
+              hipStreamSynchronize(s) == hipSuccess;
+    if (!ok) {
+      rc = VG_ERR_DEVICE;
+    } else if (rb->error) {
+      rc = VG_ERR_DEVICE;
+    } else if (rb->status == kFrameOverflow) {
+      rc = VG_ERR_GRID_OVERFLOW;
+    } else if (rb->status != kFrameOk) {
+      rc = VG_ERR_DEVICE;
+    } else {
+      *m = rb->off[1] - rb->off[0];
+    }
+  }
+  if (owned) {
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(base);
+  }
+  return rc;
+}
+
+vg_status vg_downsample(const vg_points* p, int64_t n, float leaf, vg_cells* out, int64_t* m) {
+  vg_options o;
+  std::memset(&o, 0, sizeof o);
+  o.key_mode = VG_KEY_LINEAR;
+  return vg_downsample_ex(p, n, leaf, out, m, &o);
+}
+
+vg_status vg_downsample_backward(const float* gx, const float* gy, const float* gz,
+                                 const uint32_t* count, int64_t m, const int32_t* point_cell,
+                                 int64_t n, float* dx, float* dy, float* dz, void* stream) {
+  if (n < 0 || n > INT32_MAX || m < 0) return VG_ERR_ARG;
+  if (n == 0) return VG_OK;
+  if (!point_cell || !dx || !dy || !dz) return VG_ERR_ARG;
+  if (m > 0 && (!gx || !gy || !gz || !count)) return VG_ERR_ARG;
+  const int block = 256;
+  const int64_t blocks = std::min<int64_t>(div_up(n, block), 8192);
+  hipLaunchKernelGGL(vg_backward_kernel, dim3((unsigned)blocks), dim3(block), 0,
+                     static_cast<hipStream_t>(stream), gx, gy, gz, count, m, point_cell, n, dx, dy,
+                     dz);
+  return hipGetLastError() == hipSuccess ? VG_OK : VG_ERR_DEVICE;
+}
+
+}  // extern "C"
+
+// ============================================================ batches ====
+struct vg_batch_plan {
+  int max_frames;
+  int64_t max_points;
+  int key_mode;
+  vg_tuning tuning;
+  const Variant* v;
+  Layout L;
+  void* ws_base;
+  Ws ws;
+  char* staging;       // pinned
+  float* invs;         // host scratch [max_frames]
+  int device;
+  int grid;
+  hipEvent_t done;
+  bool pending;
+  int use_graph;
+  hipGraph_t graph;
+  hipGraphExec_t gexec;
+};
+
+extern "C" {
+
+vg_status vg_batch_plan_create(int max_frames, int64_t max_total_points, vg_key_mode key_mode,
+                               const vg_tuning* tuning, vg_batch_plan** plan) {
+  if (!plan) return VG_ERR_ARG;
+  *plan = nullptr;
+  if (max_frames < 1 || max_frames > (1 << 20)) return VG_ERR_ARG;
+  if (max_total_points < 0 || max_total_points > INT32_MAX) return VG_ERR_ARG;
+  if (key_mode != VG_KEY_LINEAR && key_mode != VG_KEY_MORTON) return VG_ERR_ARG;
+  const Variant* v = find_variant(tuning);
+  if (!v) return VG_ERR_ARG;
+  vg_batch_plan* P = new (std::nothrow) vg_batch_plan();
+  if (!P) return VG_ERR_DEVICE;
+  P->max_frames = max_frames;
+  P->max_points = max_total_points;
+  P->key_mode = key_mode;
+  P->tuning = tuning ? *tuning : kDefaultTuning;
+  P->v = v;
+  P->L = make_layout(max_total_points, max_frames, *v);
+  P->ws_base = nullptr;
+  P->staging = nullptr;
+  P->invs = nullptr;
+  P->pending = false;
+  P->use_graph = 0;
+  P->graph = nullptr;
+  P->gexec = nullptr;
+  P->done = nullptr;
+  vg_status rc = VG_OK;
+  if (hipGetDevice(&P->device) != hipSuccess) rc = VG_ERR_DEVICE;
+  if (rc == VG_OK && (P->grid = grid_for(*v, &P->tuning, P->device)) <= 0) rc = VG_ERR_DEVICE;
+  if (rc == VG_OK && hipMalloc(&P->ws_base, P->L.total) != hipSuccess) rc = VG_ERR_DEVICE;
+  if (rc == VG_OK && hipHostMalloc(reinterpret_cast<void**>(&P->staging), P->L.staged,
+                                   hipHostMallocDefault) != hipSuccess)
+    rc = VG_ERR_DEVICE;
+  if (rc == VG_OK && hipEventCreateWithFlags(&P->done, hipEventDisableTiming) != hipSuccess)
+    rc = VG_ERR_DEVICE;
+  if (rc == VG_OK) {
+    P->invs = new (std::nothrow) float[max_frames];
+    if (!P->invs) rc = VG_ERR_DEVICE;
+  }
+  if (rc != VG_OK) {
+    vg_batch_plan_destroy(P);
+    return rc;
+  }
+  P->ws = carve(P->L, P->ws_base);
+  *plan = P;
+  return VG_OK;
+}
+
+vg_status vg_batch_plan_set_graph(vg_batch_plan* plan, int use_graph) {
+  if (!plan) return VG_ERR_ARG;
+  plan->use_graph = use_graph ? 1 : 0;
+  return VG_OK;
+}
+
+vg_status vg_downsample_batched(vg_batch_plan* P, const vg_points* p, const int64_t* offs,
+                                const float* leaf, int B, vg_cells* out, int64_t* out_offsets,
+                                int32_t* frame_status, void* stream) {
+  if (!P || !p || !offs || !leaf || !out || !out_offsets || !frame_status) return VG_ERR_ARG;
+  if (B < 1 || B > P->max_frames) return VG_ERR_ARG;
+  if (offs[0] != 0) return VG_ERR_ARG;
+  for (int b = 0; b < B; ++b)
+    if (offs[b + 1] < offs[b] || offs[b + 1] - offs[b] > kMaxFramePoints) return VG_ERR_ARG;
+  if (offs[B] > P->max_points) return VG_ERR_ARG;
+  if (offs[B] > 0 && (!p->x || !p->y || !p->z)) return VG_ERR_ARG;
+  if (!cells_consistent(out)) return VG_ERR_ARG;
+  for (int b = 0; b < B; ++b)
+    if (!leaf_inverse(leaf[b], &P->invs[b])) return VG_ERR_LEAF;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (P->pending) {
+    if (hipEventSynchronize(P->done) != hipSuccess) return VG_ERR_DEVICE;
+    P->pending = false;
+  }
+  CallHdr hdr;
+  if (!fill_staging(P->staging, P->L, *P->v, p, offs, leaf, P->invs, B, out, out_offsets,
+                    frame_status, P->key_mode, &hdr))
+    return VG_ERR_ARG;
+  vg_status rc = VG_OK;
+  if (P->use_graph) {
+    if (!P->gexec) {
+      hipStream_t cs;
+      if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return VG_ERR_DEVICE;
+      if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return VG_ERR_DEVICE;
+      }
+      rc = enqueue(*P->v, P->L, P->ws, P->staging, P->tuning.exec_mode, P->grid, cs);
+      hipGraph_t g = nullptr;
+      const bool ok = hipStreamEndCapture(cs, &g) == hipSuccess && rc == VG_OK &&
+                      hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0) == hipSuccess;
+      (void)hipStreamDestroy(cs);
+      if (!ok) {
+        if (g) (void)hipGraphDestroy(g);
+        P->gexec = nullptr;
+        return VG_ERR_DEVICE;
+      }
+      P->graph = g;
+    }
+    if (hipGraphLaunch(P->gexec, s) != hipSuccess) rc = VG_ERR_DEVICE;
+  } else {
+    rc = enqueue(*P->v, P->L, P->ws, P->staging, P->tuning.exec_mode, P->grid, s);
+  }
+  if (hipEventRecord(P->done, s) == hipSuccess) P->pending = true;
+  return rc;
+}
+
+vg_status vg_batch_plan_destroy(vg_batch_plan* P) {
+  if (!P) return VG_ERR_ARG;
+  if (P->pending && P->done) (void)hipEventSynchronize(P->done);
+  if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
+  if (P->graph) (void)hipGraphDestroy(P->graph);
+  if (P->done) (void)hipEventDestroy(P->done);
+  if (P->staging) (void)hipHostFree(P->staging);
+  if (P->ws_base) (void)hipFree(P->ws_base);
+  delete[] P->invs;
+  delete P;
+  return VG_OK;
+}
+
+}  // extern "C"

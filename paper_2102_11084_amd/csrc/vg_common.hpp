@@ -1,0 +1,127 @@
+// Shared definitions of the voxel-grid pipeline: workspace layout, per-frame
+// state and small device helpers.  Device and host code of libvg include it;
+// nothing here is exported.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vg {
+
+// Cells per axis are capped at 2^21: the 63-bit Morton key then fits, and
+// every cell coordinate is exact in binary32.
+constexpr float kMaxCellsPerAxis = 2097152.0f;
+constexpr int kMaxPassSlots = 11;       // ceil(63 / 6): enough for radix_bits >= 6
+constexpr int kMaxFramePoints = (1 << 30) - 1;
+
+// Look-back descriptor flags (top two bits).
+constexpr uint32_t kFlagA32 = 1u << 30;  // tile aggregate only
+constexpr uint32_t kFlagP32 = 2u << 30;  // inclusive prefix
+constexpr uint32_t kVal32 = (1u << 30) - 1;
+constexpr uint64_t kFlagA64 = 1ull << 62;
+constexpr uint64_t kFlagP64 = 2ull << 62;
+constexpr uint64_t kVal64 = (1ull << 62) - 1;
+
+enum FrameStatus : int32_t { kFrameOk = 0, kFrameOverflow = 3 };
+
+// Per-call header, copied from the host.
+struct CallHdr {
+  int32_t B;            // frames
+  int32_t key_mode;     // 0 linear, 1 Morton
+  int32_t NTs;          // sort/bbox/histogram tiles over all frames
+  int32_t NTr;          // reduce tiles over all frames
+  int64_t N;            // points over all frames
+  uint32_t want;        // output mask (kOut*)
+  uint32_t pad;
+};
+
+enum : uint32_t {
+  kOutXYZ = 1, kOutRGB = 2, kOutCount = 4, kOutKey = 8, kOutPointCell = 16, kOutRef = 32,
+  kOutLocal = 64,
+};
+
+// Per-frame description, copied from the host.
+struct FrameDesc {
+  int64_t off;   // first point of the frame in the concatenated arrays
+  int64_t n;     // points of the frame
+  float leaf;
+  float inv;     // RN32(1/leaf), computed on the host
+  int64_t pad;
+};
+
+// Per-frame state written during a call; zeroed at the start of every call.
+struct FrameState {
+  uint32_t mn_neg[3];   // max of ~enc(v)  ->  ~result = enc(min)
+  uint32_t mx[3];       // max of enc(v)
+  uint32_t n_valid;
+  uint32_t bbox_done;
+  uint32_t hist_done;
+  uint32_t pass_done[kMaxPassSlots];
+  uint32_t pad[4];
+};
+static_assert(sizeof(FrameState) == 24 * 4, "FrameState layout");
+
+// Carry-out fragment of a reduce tile: the partial sums of the segment that
+// runs past the tile's end.
+struct Frag {
+  uint32_t n;
+  float s[3];
+  float c[3];
+  uint32_t rgb[3];
+  uint32_t pad[2];
+};
+
+struct Ctl {
+  uint32_t queue[16];   // [0]: persistent queue; [1 + phase]: phased queues
+  uint32_t error;       // non-zero: a device-side wait timed out
+  uint32_t pad[15];
+};
+
+struct Io;
+
+// Device pointers of one workspace (passed to kernels by value).
+struct Ws {
+  CallHdr* hdr;
+  FrameDesc* fd;
+  uint32_t* tps;        // [B+1] sort-tile prefix over frames
+  uint32_t* tpr;        // [B+1] reduce-tile prefix over frames
+  Ctl* ctl;
+  FrameState* fs;       // [B]
+  uint32_t* hist;       // [B][slots][R]
+  uint32_t* sdesc;      // [slots][NTs][R]
+  uint64_t* rdesc;      // [NTr]
+  uint32_t* fflag;      // [NTr]
+  Frag* frag;           // [NTr]
+  uint32_t* lo[2];      // [N]
+  uint32_t* hi[2];      // [N]
+  uint32_t* idx[2];     // [N]
+  Io* io;               // inputs/outputs of the call (copied from the host)
+  // capacities the workspace was carved for
+  int32_t capB, capNTs, capNTr, slots, R;
+  int64_t capN;
+};
+
+// Inputs and outputs of one call (device pointers; the struct itself is
+// copied to device memory with the call header, so launches carry no
+// per-call arguments and can be replayed from a graph).
+struct Io {
+  const float* x;
+  const float* y;
+  const float* z;
+  const uint8_t* rgb;
+  float* cx;
+  float* cy;
+  float* cz;
+  uint8_t* crgb;
+  uint32_t* count;
+  uint64_t* key;
+  int32_t* point_cell;
+  uint32_t* ref_index;
+  float* lx;
+  float* ly;
+  float* lz;
+  int64_t* out_offsets;  // [B+1]
+  int32_t* frame_status; // [B]
+};
+
+}  // namespace vg

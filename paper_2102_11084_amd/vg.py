@@ -1,0 +1,285 @@
+"""Thin Python binding of libvg.so (ctypes): argument marshalling only.
+
+Every step of the downsampling runs in the HIP library; torch provides the
+device memory (outputs, workspace) and the current stream.  If libvg.so is
+missing the calls raise: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvg.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "vg.h")
+
+VG_OK, VG_ERR_ARG, VG_ERR_LEAF, VG_ERR_GRID_OVERFLOW, VG_ERR_WORKSPACE, VG_ERR_DEVICE = range(6)
+KEY_LINEAR, KEY_MORTON = 0, 1
+EXEC_PERSISTENT, EXEC_PHASED = 0, 1
+
+P = ctypes.c_void_p
+
+
+class vg_points(ctypes.Structure):
+    _fields_ = [("x", P), ("y", P), ("z", P), ("rgb", P)]
+
+
+class vg_cells(ctypes.Structure):
+    _fields_ = [("x", P), ("y", P), ("z", P), ("rgb", P), ("count", P), ("key", P),
+                ("point_cell", P), ("ref_index", P), ("lx", P), ("ly", P), ("lz", P)]
+
+
+class vg_tuning(ctypes.Structure):
+    _fields_ = [("sort_block", ctypes.c_int), ("sort_items", ctypes.c_int),
+                ("radix_bits", ctypes.c_int), ("reduce_block", ctypes.c_int),
+                ("reduce_items", ctypes.c_int), ("blocks_per_cu", ctypes.c_int),
+                ("exec_mode", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class vg_options(ctypes.Structure):
+    _fields_ = [("stream", P), ("workspace", P), ("workspace_bytes", ctypes.c_size_t),
+                ("key_mode", ctypes.c_int), ("tuning", ctypes.POINTER(vg_tuning))]
+
+
+class VGError(RuntimeError):
+    def __init__(self, status, where=""):
+        self.status = status
+        msg = _lib_handle.vg_status_string(status).decode() if _lib_handle else str(status)
+        super().__init__(f"{where}: {msg}" if where else msg)
+
+
+_lib_handle = None
+
+EXPORTS = ["vg_status_string", "vg_default_tuning", "vg_tuning_supported", "vg_workspace_bytes",
+           "vg_downsample", "vg_downsample_ex", "vg_downsample_backward", "vg_batch_plan_create",
+           "vg_batch_plan_set_graph", "vg_downsample_batched", "vg_batch_plan_destroy"]
+
+
+def lib():
+    """The loaded libvg.so (raises if it has not been built)."""
+    global _lib_handle
+    if _lib_handle is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        L.vg_status_string.argtypes = [ctypes.c_int]
+        L.vg_status_string.restype = ctypes.c_char_p
+        L.vg_default_tuning.argtypes = [ctypes.POINTER(vg_tuning)]
+        L.vg_tuning_supported.argtypes = [ctypes.POINTER(vg_tuning)]
+        L.vg_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.POINTER(vg_tuning)]
+        L.vg_workspace_bytes.restype = ctypes.c_size_t
+        L.vg_downsample.argtypes = [ctypes.POINTER(vg_points), ctypes.c_int64, ctypes.c_float,
+                                    ctypes.POINTER(vg_cells), ctypes.POINTER(ctypes.c_int64)]
+        L.vg_downsample_ex.argtypes = L.vg_downsample.argtypes + [ctypes.POINTER(vg_options)]
+        L.vg_downsample_backward.argtypes = [P, P, P, P, ctypes.c_int64, P, ctypes.c_int64, P, P,
+                                             P, P]
+        L.vg_batch_plan_create.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int,
+                                           ctypes.POINTER(vg_tuning), ctypes.POINTER(P)]
+        L.vg_batch_plan_set_graph.argtypes = [P, ctypes.c_int]
+        L.vg_downsample_batched.argtypes = [P, ctypes.POINTER(vg_points), P, P, ctypes.c_int,
+                                            ctypes.POINTER(vg_cells), P, P, P]
+        L.vg_batch_plan_destroy.argtypes = [P]
+        for name in EXPORTS:
+            if name != "vg_status_string" and name != "vg_workspace_bytes":
+                getattr(L, name).restype = ctypes.c_int
+        _lib_handle = L
+    return _lib_handle
+
+
+def default_tuning(**over) -> vg_tuning:
+    t = vg_tuning()
+    lib().vg_default_tuning(ctypes.byref(t))
+    for k, v in over.items():
+        setattr(t, k, int(v))
+    return t
+
+
+def tuning_supported(t: vg_tuning) -> bool:
+    return lib().vg_tuning_supported(ctypes.byref(t)) == VG_OK
+
+
+def workspace_bytes(n_total: int, n_frames: int = 1, tuning: vg_tuning | None = None) -> int:
+    return int(lib().vg_workspace_bytes(int(n_total), int(n_frames),
+                                        ctypes.byref(tuning) if tuning is not None else None))
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check_points(x, y, z, rgb):
+    n = x.numel()
+    for t in (x, y, z):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.numel() == n):
+            raise ValueError("x, y, z must be contiguous float32 CUDA tensors of equal length")
+    if rgb is not None and not (rgb.is_cuda and rgb.dtype == torch.uint8 and rgb.is_contiguous()
+                                and rgb.numel() == 3 * n):
+        raise ValueError("rgb must be a contiguous uint8 CUDA tensor of n x 3 values")
+    return n
+
+
+ALL_OUTPUTS = ("xyz", "rgb", "count", "key", "point_cell", "ref_index", "local")
+
+
+def _alloc_cells(cap, n_points, dev, outputs, have_rgb):
+    o = {}
+    f32 = dict(dtype=torch.float32, device=dev)
+    if "xyz" in outputs:
+        o["x"], o["y"], o["z"] = (torch.empty(cap, **f32) for _ in range(3))
+    if "rgb" in outputs and have_rgb:
+        o["rgb"] = torch.empty((cap, 3), dtype=torch.uint8, device=dev)
+    if "count" in outputs:
+        o["count"] = torch.empty(cap, dtype=torch.int32, device=dev)  # holds uint32
+    if "key" in outputs:
+        o["key"] = torch.empty(cap, dtype=torch.int64, device=dev)    # holds uint64
+    if "point_cell" in outputs:
+        o["point_cell"] = torch.empty(n_points, dtype=torch.int32, device=dev)
+    if "ref_index" in outputs:
+        o["ref_index"] = torch.empty(cap, dtype=torch.int32, device=dev)  # holds uint32
+    if "local" in outputs:
+        o["lx"], o["ly"], o["lz"] = (torch.empty(cap, **f32) for _ in range(3))
+    cells = vg_cells(*(_ptr(o.get(k)) for k in ("x", "y", "z", "rgb", "count", "key",
+                                                    "point_cell", "ref_index", "lx", "ly", "lz")))
+    return o, cells
+
+
+def voxel_downsample(x, y, z, rgb=None, leaf=0.05, key_mode=KEY_LINEAR, tuning=None,
+                     outputs=ALL_OUTPUTS, workspace=None):
+    """Voxel-grid centroid filter of one cloud on the GPU (libvg: vg_downsample_ex).
+
+    x, y, z: float32 CUDA tensors [n]; rgb: uint8 CUDA tensor [n, 3] or None.
+    Returns a dict of tensors trimmed to the m occupied cells (point_cell has n
+    entries) plus "m".  count/ref_index are int32 views of uint32 values; key
+    is an int64 view of the uint64 key.
+    """
+    n = _check_points(x, y, z, rgb)
+    dev = x.device
+    o, cells = _alloc_cells(max(n, 1), n, dev, outputs, rgb is not None)
+    pts = vg_points(_ptr(x), _ptr(y), _ptr(z), _ptr(rgb))
+    wsb = workspace_bytes(max(n, 1), 1, tuning)
+    if workspace is None or workspace.numel() < wsb:
+        workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    opts = vg_options(ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream),
+                      ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), int(key_mode),
+                      ctypes.pointer(tuning) if tuning is not None else None)
+    m = ctypes.c_int64(0)
+    st = lib().vg_downsample_ex(ctypes.byref(pts), n, ctypes.c_float(leaf), ctypes.byref(cells),
+                                ctypes.byref(m), ctypes.byref(opts))
+    if st != VG_OK:
+        raise VGError(st, "vg_downsample_ex")
+    mm = int(m.value)
+    res = {k: (v if k == "point_cell" else v[:mm]) for k, v in o.items()}
+    res["m"] = mm
+    return res
+
+
+def downsample_backward(gx, gy, gz, count, point_cell):
+    """dL/dxyz for upstream dL/dcentroid (libvg: vg_downsample_backward)."""
+    n = point_cell.numel()
+    m = count.numel()
+    dev = point_cell.device
+    dx, dy, dz = (torch.empty(n, dtype=torch.float32, device=dev) for _ in range(3))
+    for t in (gx, gy, gz):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.numel() == m):
+            raise ValueError("gradients must be contiguous float32 CUDA tensors [m]")
+    st = lib().vg_downsample_backward(_ptr(gx), _ptr(gy), _ptr(gz), _ptr(count), m,
+                                      _ptr(point_cell), n, _ptr(dx), _ptr(dy), _ptr(dz),
+                                      ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream))
+    if st != VG_OK:
+        raise VGError(st, "vg_downsample_backward")
+    return dx, dy, dz
+
+
+class VoxelDownsampleFn(torch.autograd.Function):
+    """Centroids of the voxel grid as a differentiable function of x, y, z.
+
+    The cell assignment (and so the grid) is held fixed in the backward pass:
+    dL/dp_i = dL/dc[cell(i)] / count[cell(i)], zero for invalid points.
+    """
+
+    @staticmethod
+    def forward(ctx, x, y, z, leaf, key_mode=KEY_LINEAR):
+        r = voxel_downsample(x, y, z, None, leaf, key_mode,
+                             outputs=("xyz", "count", "point_cell"))
+        ctx.save_for_backward(r["count"], r["point_cell"])
+        ctx.mark_non_differentiable(r["count"])
+        return r["x"], r["y"], r["z"], r["count"]
+
+    @staticmethod
+    def backward(ctx, gx, gy, gz, gcount):
+        count, pc = ctx.saved_tensors
+        m = count.numel()
+        dev = pc.device
+        gx, gy, gz = (g.contiguous() if g is not None else torch.zeros(m, device=dev)
+                      for g in (gx, gy, gz))
+        dx, dy, dz = downsample_backward(gx, gy, gz, count, pc)
+        return dx, dy, dz, None, None
+
+
+def voxel_downsample_autograd(x, y, z, leaf, key_mode=KEY_LINEAR):
+    return VoxelDownsampleFn.apply(x, y, z, leaf, key_mode)
+
+
+class BatchPlan:
+    """Many frames of uneven size and leaf in one launch (vg_downsample_batched)."""
+
+    def __init__(self, max_frames, max_total_points, key_mode=KEY_LINEAR, tuning=None,
+                 use_graph=False):
+        self._h = ctypes.c_void_p()
+        self.tuning = tuning
+        st = lib().vg_batch_plan_create(int(max_frames), int(max_total_points), int(key_mode),
+                                        ctypes.byref(tuning) if tuning is not None else None,
+                                        ctypes.byref(self._h))
+        if st != VG_OK:
+            raise VGError(st, "vg_batch_plan_create")
+        self.max_frames = int(max_frames)
+        self.max_total_points = int(max_total_points)
+        self.set_graph(use_graph)
+
+    def set_graph(self, use_graph: bool):
+        st = lib().vg_batch_plan_set_graph(self._h, 1 if use_graph else 0)
+        if st != VG_OK:
+            raise VGError(st, "vg_batch_plan_set_graph")
+
+    def alloc_outputs(self, n_total, B, dev, outputs=ALL_OUTPUTS, have_rgb=True):
+        o, cells = _alloc_cells(max(n_total, 1), n_total, dev, outputs, have_rgb)
+        o["out_offsets"] = torch.empty(B + 1, dtype=torch.int64, device=dev)
+        o["frame_status"] = torch.empty(B, dtype=torch.int32, device=dev)
+        return o, cells
+
+    def run(self, x, y, z, rgb, frame_offsets, leaves, outputs=ALL_OUTPUTS, out=None):
+        """Asynchronous launch; returns untrimmed output tensors (see out_offsets)."""
+        n = _check_points(x, y, z, rgb)
+        offs = np.ascontiguousarray(frame_offsets, dtype=np.int64)
+        lv = np.ascontiguousarray(leaves, dtype=np.float32)
+        B = lv.size
+        if offs.size != B + 1 or offs[-1] != n:
+            raise ValueError("frame_offsets must have B+1 entries ending at n")
+        if out is None:
+            out = self.alloc_outputs(n, B, x.device, outputs, rgb is not None)
+        o, cells = out
+        pts = vg_points(_ptr(x), _ptr(y), _ptr(z), _ptr(rgb))
+        st = lib().vg_downsample_batched(
+            self._h, ctypes.byref(pts), ctypes.c_void_p(offs.ctypes.data),
+            ctypes.c_void_p(lv.ctypes.data), B, ctypes.byref(cells), _ptr(o["out_offsets"]),
+            _ptr(o["frame_status"]), ctypes.c_void_p(torch.cuda.current_stream(x.device).cuda_stream))
+        if st != VG_OK:
+            raise VGError(st, "vg_downsample_batched")
+        return o
+
+    def close(self):
+        if self._h:
+            lib().vg_batch_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

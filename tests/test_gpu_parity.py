@@ -1,0 +1,183 @@
+"""libvg on the GPU against the CPU oracle, element by element.
+
+Keys, cell order, counts, first indices, per-point rows and colours must match
+bit for bit; centroids within 1e-6 of the leaf plus one binary32 ulp of the
+centroid, local means (p - p_ref) within 1e-6 of the leaf.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import assert_matches_oracle, gpu_downsample, host, to_dev
+from paper_2102_11084_amd import datagen as dg
+from paper_2102_11084_amd import vg
+
+pytestmark = pytest.mark.gpu
+
+
+def random_cloud(n, seed, side=2.0, nan_frac=0.1, blobs=False):
+    rng = np.random.default_rng(seed)
+    if blobs:
+        centres = rng.uniform(0, side, size=(max(1, n // 5000), 3))
+        p = centres[rng.integers(0, len(centres), n)] + rng.normal(0, side / 200, size=(n, 3))
+    else:
+        p = rng.uniform(0, side, size=(n, 3))
+    p = p.astype(np.float32)
+    bad = rng.random(n) < nan_frac
+    axis = rng.integers(0, 3, n)
+    vals = np.array([np.nan, np.inf, -np.inf], np.float32)[rng.integers(0, 3, n)]
+    p[bad, axis[bad]] = vals[bad]
+    rgb = rng.integers(0, 256, size=(n, 3), dtype=np.uint8)
+    return p[:, 0].copy(), p[:, 1].copy(), p[:, 2].copy(), rgb
+
+
+def run_both(x, y, z, rgb, leaf, key_mode=vg.KEY_LINEAR, tuning=None):
+    g = gpu_downsample(x, y, z, rgb, leaf, key_mode, tuning)
+    o = oracle.downsample(x, y, z, rgb, leaf, key_mode)
+    return g, o
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 4095, 4096, 4097, 8193, 20000, 123457])
+def test_random_uniform(n):
+    print(f"case n={n}", flush=True)
+    x, y, z, rgb = random_cloud(n, seed=n)
+    leaf = 0.05
+    g, o = run_both(x, y, z, rgb, leaf)
+    assert_matches_oracle(g, o, leaf)
+
+
+@pytest.mark.parametrize("n,leaf", [(50000, 0.01), (150000, 0.02), (300001, 0.1)])
+def test_random_blobs(n, leaf):
+    print(f"case blobs n={n} leaf={leaf}", flush=True)
+    x, y, z, rgb = random_cloud(n, seed=7 + n, blobs=True)
+    g, o = run_both(x, y, z, rgb, leaf)
+    assert_matches_oracle(g, o, leaf)
+
+
+@pytest.mark.parametrize("key_mode", [vg.KEY_LINEAR, vg.KEY_MORTON])
+def test_frame_640x480(key_mode):
+    x, y, z, rgb = dg.frame_640x480()
+    g, o = run_both(x, y, z, rgb, 0.05, key_mode)
+    assert_matches_oracle(g, o, 0.05)
+
+
+@pytest.mark.parametrize("leaf", [0.01, 0.02, 0.05, 0.10])
+def test_frame_1280x720_sweep(leaf):
+    x, y, z, rgb = dg.frame_1280x720()
+    g, o = run_both(x, y, z, rgb, leaf)
+    assert_matches_oracle(g, o, leaf)
+
+
+@pytest.mark.parametrize("key_mode", [vg.KEY_LINEAR, vg.KEY_MORTON])
+def test_wide_keys(key_mode):
+    # about 2000^3 cells: linear keys need 33 bits, Morton keys 33 bits
+    rng = np.random.default_rng(3)
+    p = rng.uniform(0, 1000, size=(60000, 3)).astype(np.float32)
+    p[0] = 0.0
+    p[1] = 999.9
+    rgb = rng.integers(0, 256, size=(60000, 3), dtype=np.uint8)
+    g, o = run_both(p[:, 0].copy(), p[:, 1].copy(), p[:, 2].copy(), rgb, 0.5, key_mode)
+    assert int(o["key"].max()) >= 2 ** 32
+    assert_matches_oracle(g, o, 0.5)
+
+
+def test_cells_spanning_many_tiles():
+    # three cells of ~100k points each: every cell spans many reduce tiles
+    rng = np.random.default_rng(11)
+    n = 300000
+    which = rng.integers(0, 3, n)
+    p = (which[:, None] * 1.0 + rng.uniform(0.0, 0.9, size=(n, 3))).astype(np.float32)
+    rgb = rng.integers(0, 256, size=(n, 3), dtype=np.uint8)
+    g, o = run_both(p[:, 0].copy(), p[:, 1].copy(), p[:, 2].copy(), rgb, 1.0)
+    assert o["m"] == 3
+    assert_matches_oracle(g, o, 1.0)
+
+
+def test_single_cell_large():
+    x, y, z, rgb = random_cloud(1_000_000, seed=5, side=1.0, nan_frac=0.05)
+    g, o = run_both(x, y, z, rgb, 4.0)
+    assert o["m"] == 1
+    assert_matches_oracle(g, o, 4.0)
+
+
+def test_tiny_leaf_returns_the_points():
+    rng = np.random.default_rng(4)
+    lat = rng.integers(0, 512, size=(3000, 3)).astype(np.float32) / np.float32(512.0)
+    p = lat[rng.integers(0, 3000, size=20000)]
+    rgb = rng.integers(0, 256, size=(20000, 3), dtype=np.uint8)
+    g, o = run_both(p[:, 0].copy(), p[:, 1].copy(), p[:, 2].copy(), rgb, 1e-6)
+    assert_matches_oracle(g, o, 1e-6)
+    cent = np.stack([g["x"], g["y"], g["z"]], 1)
+    uniq = np.unique(p, axis=0)
+    assert g["m"] == len(uniq)
+    assert {tuple(c) for c in cent} == {tuple(u) for u in uniq}
+
+
+def test_edge_cases():
+    e = np.zeros(0, np.float32)
+    assert gpu_downsample(e, e, e, None, 0.1)["m"] == 0
+    nan = np.full(1000, np.nan, np.float32)
+    g = gpu_downsample(nan, nan, nan, None, 0.1)
+    assert g["m"] == 0 and (g["point_cell"] == -1).all()
+    one = np.array([1.5], np.float32)
+    g, o = run_both(one, one, one, np.array([[1, 2, 3]], np.uint8), 0.1)
+    assert_matches_oracle(g, o, 0.1)
+    # subnormal leaf and subnormal coordinate differences: nothing may flush to zero
+    t126 = np.float32(2.0 ** -126)
+    x = np.array([t126, np.float32(1.5) * t126, np.float32(2.0) * t126], np.float32)
+    zz = np.zeros(3, np.float32)
+    g, o = run_both(x, zz.copy(), zz.copy(), None, float(np.float32(2.0 ** -127)))
+    assert list(g["key"]) == [0, 1, 2]
+    # signed zeros share a cell
+    x = np.array([-0.0, 0.0, 0.3], np.float32)
+    g, o = run_both(x, zz.copy(), zz.copy(), None, 0.25)
+    assert_matches_oracle(g, o, 0.25)
+
+
+def test_grid_overflow_reported():
+    x = np.array([0.0, 2097152.0], np.float32)
+    zz = np.zeros(2, np.float32)
+    with pytest.raises(vg.VGError) as e:
+        gpu_downsample(x, zz, zz, None, 1.0)
+    assert e.value.status == vg.VG_ERR_GRID_OVERFLOW
+    x = np.array([0.0, 2097151.0], np.float32)
+    g, o = run_both(x, zz.copy(), zz.copy(), None, 1.0)
+    assert_matches_oracle(g, o, 1.0)
+
+
+def test_deterministic():
+    x, y, z, rgb = random_cloud(200000, seed=9, blobs=True)
+    a = gpu_downsample(x, y, z, rgb, 0.02)
+    b = gpu_downsample(x, y, z, rgb, 0.02)
+    for k in a:
+        if k != "m":
+            assert np.array_equal(a[k].view(np.uint8), b[k].view(np.uint8)), k
+
+
+def supported_tunings():
+    out = []
+    for block, si, rb, ri in [(256, 16, 8, 8), (256, 8, 8, 8), (256, 12, 8, 8), (256, 16, 8, 4),
+                              (256, 16, 7, 8), (512, 8, 8, 4), (512, 8, 8, 8), (256, 16, 6, 8)]:
+        for mode in (vg.EXEC_PERSISTENT, vg.EXEC_PHASED):
+            out.append(dict(sort_block=block, sort_items=si, radix_bits=rb, reduce_block=block,
+                            reduce_items=ri, exec_mode=mode))
+    return out
+
+
+@pytest.mark.parametrize("tune", supported_tunings(), ids=lambda t: "-".join(str(v) for v in t.values()))
+def test_every_tuning_matches_oracle(tune):
+    print(f"case tuning {tune}", flush=True)
+    t = vg.default_tuning(**tune)
+    x, y, z, rgb = random_cloud(90000, seed=21, blobs=True)
+    g, o = run_both(x, y, z, rgb, 0.02, tuning=t)
+    assert_matches_oracle(g, o, 0.02)
+
+
+def test_exec_modes_bit_identical():
+    x, y, z, rgb = dg.frame_640x480()
+    a = gpu_downsample(x, y, z, rgb, 0.02, tuning=vg.default_tuning(exec_mode=vg.EXEC_PERSISTENT))
+    b = gpu_downsample(x, y, z, rgb, 0.02, tuning=vg.default_tuning(exec_mode=vg.EXEC_PHASED))
+    for k in a:
+        if k != "m":
+            assert np.array_equal(a[k].view(np.uint8), b[k].view(np.uint8)), k
