@@ -1,0 +1,246 @@
+#!/usr/bin/env python3
+"""Voxel-grid downsampling throughput on one MI355X (libvg).
+
+Step = one batched call over the uneven 64-frame RGB-D batch (every frame
+through bbox, histogram, radix sort and segmented reduce, one persistent
+launch replayed from a hipGraph), inputs resident in HBM.  Prints one JSON
+line: Mpoints/s (input points, valid and invalid), the roofline of the
+pipeline kernel, the plain per-frame path and the backward on the same GPU,
+and the CPU oracle on a bounded sample.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "Mpoints/s voxel downsample + % HBM roofline; batched vs plain at 1e-6 tol"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def frame_passes(x, y, z, leaf, radix_bits):
+    """Radix passes of a frame under the library's rule (host-side accounting only)."""
+    v = np.isfinite(x) & np.isfinite(y) & np.isfinite(z)
+    if not v.any():
+        return 0
+    inv = np.float32(1.0) / np.float32(leaf)
+    dims = []
+    for a in (x, y, z):
+        av = a[v]
+        t = (av.max() - av.min()) * inv
+        dims.append(int(np.floor(t)) + 1)
+    top = dims[0] * dims[1] * dims[2] - 1
+    bits = top.bit_length()
+    return max(1, math.ceil(bits / radix_bits))
+
+
+def algorithmic_bytes(n, nv, passes, m):
+    """Bytes the sort-based method moves per call: bbox and key read xyz of every
+    point (12 + 12 B), the key pass writes (key, index) of valid points (8 B),
+    the histogram reads keys (4 B), each radix pass reads and writes pairs
+    (16 B), the reduce reads pairs (8 B) and gathers xyz + rgb (15 B) and writes
+    the per-point row (4 B), and every cell writes xyz, rgb, count, key (27 B)."""
+    return 24 * n + (8 + 4 + 16 * passes + 8 + 15 + 4) * nv + 27 * m
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--frames", type=int, default=64)
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--exec-mode", choices=["persistent", "phased"], default="persistent")
+    ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2102_11084_amd", "tuning_gfx950.json"))
+    ap.add_argument("--no-legs", action="store_true", help="skip plain/backward legs")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (frames shard across GPUs by design, "
+              "but no multi-GPU path is built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2102_11084_amd import datagen as dg
+    from paper_2102_11084_amd import vg
+
+    dev = torch.device("cuda:0")
+    tuning = vg.load_tuning(args.tuning) if os.path.exists(args.tuning) else vg.default_tuning()
+    if args.exec_mode == "phased":
+        tuning.exec_mode = vg.EXEC_PHASED
+    log(f"tuning {tuning.as_dict()}")
+
+    t0 = time.time()
+    x, y, z, rgb, offs, leaves = dg.batch(args.frames)
+    N = int(offs[-1])
+    nv_frames = np.array([int(np.isfinite(z[offs[b]:offs[b + 1]]).sum()) for b in range(len(leaves))])
+    log(f"generated {len(leaves)} frames, {N} points ({nv_frames.sum()} valid) in {time.time() - t0:.1f}s")
+    d = [torch.from_numpy(a).to(dev) for a in (x, y, z, rgb.reshape(-1))]
+    plan = vg.BatchPlan(len(leaves), N, vg.KEY_LINEAR, tuning, use_graph=not args.no_graph)
+    outs = plan.alloc_outputs(N, len(leaves), dev, outputs=("xyz", "rgb", "count", "key", "point_cell"))
+    stream = torch.cuda.current_stream(dev)
+
+    for _ in range(args.warmup):
+        plan.run(*d, offs, leaves, out=outs)
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for i in range(args.steps):
+        starts[i].record(stream)
+        plan.run(*d, offs, leaves, out=outs)
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ev_ms = float(np.mean([s.elapsed_time(e) for s, e in zip(starts, ends)]))
+    ms_per_step = wall * 1e3 / args.steps
+    value = N / (ms_per_step * 1e-3) / 1e6
+    log(f"batched: {ms_per_step:.3f} ms/step (events {ev_ms:.3f} ms), {value:.1f} Mpoints/s")
+
+    o = {k: v.cpu().numpy() for k, v in outs[0].items()}
+    assert (o["frame_status"] == 0).all(), "a frame failed"
+    m_frames = np.diff(o["out_offsets"])
+    radix = tuning.radix_bits
+    passes = np.array([frame_passes(x[offs[b]:offs[b + 1]], y[offs[b]:offs[b + 1]],
+                                    z[offs[b]:offs[b + 1]], leaves[b], radix) for b in range(len(leaves))])
+    alg = sum(algorithmic_bytes(int(offs[b + 1] - offs[b]), int(nv_frames[b]), int(passes[b]),
+                                int(m_frames[b])) for b in range(len(leaves)))
+    achieved = alg / (ev_ms * 1e-3) / 1e9
+    floor_bytes = 15 * int(nv_frames.sum()) + 27 * int(m_frames.sum())
+    result = {
+        "metric": METRIC, "value": round(value, 2), "unit": "Mpoints/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded ray-cast RGB-D frames standing in for the paper's corridor data)",
+        "config": {
+            "workload": f"batched: {len(leaves)} uneven RGB-D frames, 50k-900k valid points each, "
+                        "per-frame leaf in {0.02, 0.05, 0.10} m, one persistent launch replayed "
+                        "from a hipGraph",
+            "frames": int(len(leaves)), "points": N, "valid_points": int(nv_frames.sum()),
+            "cells": int(m_frames.sum()), "radix_passes": [int(p) for p in passes],
+            "tuning": tuning.as_dict(), "graph": not args.no_graph,
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "vg_pipeline_kernel (persistent)",
+            "algorithmic_bytes_per_launch": int(alg),
+            "kernel_ms_events": round(ev_ms, 4),
+            "floor_frac": round(floor_bytes / (ev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        },
+    }
+
+    if not args.no_legs:
+        # plain per-frame path: one synchronous vg_downsample_ex per frame
+        ws = torch.empty(vg.workspace_bytes(int(np.diff(offs).max()), 1, tuning), dtype=torch.uint8,
+                         device=dev)
+        frames_dev = [[t[int(offs[b]) * (3 if t is d[3] else 1):int(offs[b + 1]) * (3 if t is d[3] else 1)]
+                       for t in d] for b in range(len(leaves))]
+        for rep in range(2):
+            torch.cuda.synchronize()
+            p0 = time.perf_counter()
+            for b in range(len(leaves)):
+                vg.voxel_downsample(*frames_dev[b], leaf=float(leaves[b]), tuning=tuning,
+                                    outputs=("xyz", "rgb", "count", "key", "point_cell"), workspace=ws)
+            torch.cuda.synchronize()
+            plain_s = time.perf_counter() - p0
+        plain = N / plain_s / 1e6
+        log(f"plain per-frame: {plain_s * 1e3:.2f} ms, {plain:.1f} Mpoints/s")
+        # backward leg: 32 clouds of 100k points, leaf 0.05, one batched forward + one backward
+        cl = [dg.uniform_cloud(100_000, seed=5000 + c) for c in range(32)]
+        bx = [torch.from_numpy(np.concatenate([c[a] for c in cl])).to(dev) for a in range(3)]
+        boffs = np.arange(33, dtype=np.int64) * 100_000
+        bplan = vg.BatchPlan(32, 3_200_000, vg.KEY_LINEAR, tuning)
+        bleaf = np.full(32, 0.05, np.float32)
+        bout = bplan.alloc_outputs(3_200_000, 32, dev, outputs=("xyz", "count", "point_cell"),
+                                   have_rgb=False)
+        bo = bplan.run(bx[0], bx[1], bx[2], None, boffs, bleaf, out=bout)
+        torch.cuda.synchronize()
+        mt = int(bo["out_offsets"][-1].item())
+        G = torch.randn(mt, 3, device=dev)
+        gx, gy, gz = (G[:, a].contiguous() for a in range(3))
+        cnt = bo["count"][:mt]
+        for _ in range(3):
+            vg.downsample_backward(gx, gy, gz, cnt, bo["point_cell"])
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(20):
+            vg.downsample_backward(gx, gy, gz, cnt, bo["point_cell"])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        bwd_ms = e0.elapsed_time(e1) / 20
+        f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        f0.record(stream)
+        for _ in range(10):
+            bplan.run(bx[0], bx[1], bx[2], None, boffs, bleaf, out=bout)
+        f1.record(stream)
+        torch.cuda.synchronize()
+        fwd_ms = f0.elapsed_time(f1) / 10
+        bplan.close()
+        result["legs"] = {
+            "plain_per_frame_mpoints_s": round(plain, 2),
+            "batched_over_plain": round(value / plain, 2),
+            "backward_32x100k": {"forward_ms": round(fwd_ms, 4), "backward_ms": round(bwd_ms, 4),
+                                 "backward_mpoints_s": round(3_200_000 / (bwd_ms * 1e-3) / 1e6, 1),
+                                 "backward_gbs": round(32 * 3_200_000 / (bwd_ms * 1e-3) / 1e9, 1)},
+        }
+
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.load()
+        used, pts, nfr = 0.0, 0, 0
+        for b in range(len(leaves)):
+            s0, s1 = int(offs[b]), int(offs[b + 1])
+            c0 = time.perf_counter()
+            oracle.downsample(x[s0:s1], y[s0:s1], z[s0:s1], rgb[s0:s1], float(leaves[b]))
+            used += time.perf_counter() - c0
+            pts += s1 - s0
+            nfr += 1
+            if used >= args.cpu_seconds:
+                break
+        result["cpu_baseline"] = {
+            "value": round(pts / used / 1e6, 3), "unit": "Mpoints/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {nfr} of {len(leaves)} frames ({pts} points), single-threaded "
+                      f"std::map oracle, {used:.1f} s",
+            "host_cpu": _cpu_name(), "host_cores": os.cpu_count(),
+        }
+        log(f"cpu oracle: {result['cpu_baseline']['value']} Mpoints/s on 1 core")
+
+    plan.close()
+    print(json.dumps(result), flush=True)
+
+
+def _cpu_name():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+if __name__ == "__main__":
+    main()

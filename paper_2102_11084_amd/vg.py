@@ -100,6 +100,15 @@ def default_tuning(**over) -> vg_tuning:
     return t
 
 
+def load_tuning(path: str) -> vg_tuning:
+    """Tuning written by the autotuner (JSON object with vg_tuning's fields)."""
+    import json
+    with open(path) as f:
+        d = json.load(f)
+    d = d.get("tuning", d)
+    return default_tuning(**{k: d[k] for k, _ in vg_tuning._fields_ if k in d})
+
+
 def tuning_supported(t: vg_tuning) -> bool:
     return lib().vg_tuning_supported(ctypes.byref(t)) == VG_OK
 

@@ -1,0 +1,155 @@
+"""Batched form on the GPU: per-frame oracle parity, plain-vs-batched, graph replay."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import assert_matches_oracle, gpu_downsample, host, to_dev
+from paper_2102_11084_amd import datagen as dg
+from paper_2102_11084_amd import vg
+
+pytestmark = pytest.mark.gpu
+
+
+def small_batch(seed=0):
+    """Uneven frames: RGB-D frames of several sizes, an empty frame, an all-NaN
+    frame, an overflowing frame, a single point."""
+    rng = np.random.default_rng(seed)
+    frames, leaves = [], []
+    for i, (W, H) in enumerate([(64, 48), (160, 120), (320, 240), (97, 33), (200, 150)]):
+        frames.append(dg.rgbd_frame(W, H, seed=100 + i + seed))
+        leaves.append(float(rng.choice([0.02, 0.05, 0.1])))
+    e = np.zeros(0, np.float32)
+    frames.insert(2, (e, e, e, np.zeros((0, 3), np.uint8)))
+    leaves.insert(2, 0.05)
+    nan = np.full(777, np.nan, np.float32)
+    frames.insert(4, (nan, nan.copy(), nan.copy(), np.zeros((777, 3), np.uint8)))
+    leaves.insert(4, 0.05)
+    ov = np.array([0.0, 1e4, 5.0], np.float32)
+    frames.insert(5, (ov, np.zeros(3, np.float32), np.zeros(3, np.float32),
+                      np.full((3, 3), 9, np.uint8)))
+    leaves.insert(5, 1e-3)
+    one = np.array([0.25], np.float32)
+    frames.append((one, one.copy(), one.copy(), np.array([[1, 2, 3]], np.uint8)))
+    leaves.append(0.1)
+    offs = np.zeros(len(frames) + 1, np.int64)
+    offs[1:] = np.cumsum([f[0].size for f in frames])
+    cat = [np.concatenate([f[a] for f in frames]) for a in range(4)]
+    return cat[0], cat[1], cat[2], cat[3], offs, np.array(leaves, np.float32)
+
+
+def run_batched(x, y, z, rgb, offs, leaves, plan=None, key_mode=vg.KEY_LINEAR, tuning=None):
+    d = to_dev(x, y, z, rgb.reshape(-1))
+    own = plan is None
+    if own:
+        plan = vg.BatchPlan(len(leaves), x.size, key_mode, tuning)
+    o = plan.run(*d, offs, leaves)
+    torch.cuda.synchronize()
+    if own:
+        plan.close()
+    return host({k: v for k, v in o.items()})
+
+
+def check_against_oracle(g, x, y, z, rgb, offs, leaves, key_mode=vg.KEY_LINEAR):
+    res, status = oracle.downsample_batched(x, y, z, rgb, offs, leaves, key_mode)
+    assert list(g["frame_status"]) == status
+    oo = g["out_offsets"]
+    assert oo[0] == 0
+    for b, (r, s) in enumerate(zip(res, status)):
+        lo, hi = int(oo[b]), int(oo[b + 1])
+        s0, s1 = int(offs[b]), int(offs[b + 1])
+        if s != oracle.OK:
+            assert hi == lo
+            assert (g["point_cell"][s0:s1] == -1).all()
+            continue
+        fr = {k: g[k][lo:hi] for k in ("x", "y", "z", "rgb", "count", "key", "ref_index",
+                                       "lx", "ly", "lz")}
+        fr["point_cell"] = g["point_cell"][s0:s1]
+        fr["m"] = hi - lo
+        assert_matches_oracle(fr, r, float(leaves[b]), point_cell_offset=lo, ref_offset=s0)
+
+
+@pytest.mark.parametrize("key_mode", [vg.KEY_LINEAR, vg.KEY_MORTON])
+def test_small_batch_matches_per_frame_oracle(key_mode):
+    x, y, z, rgb, offs, leaves = small_batch()
+    g = run_batched(x, y, z, rgb, offs, leaves, key_mode=key_mode)
+    check_against_oracle(g, x, y, z, rgb, offs, leaves, key_mode)
+
+
+@pytest.mark.parametrize("mode", [vg.EXEC_PERSISTENT, vg.EXEC_PHASED])
+def test_batched_equals_plain_bitwise(mode):
+    x, y, z, rgb, offs, leaves = small_batch(seed=1)
+    t = vg.default_tuning(exec_mode=mode)
+    g = run_batched(x, y, z, rgb, offs, leaves, tuning=t)
+    for b in range(len(leaves)):
+        s0, s1 = int(offs[b]), int(offs[b + 1])
+        lo, hi = int(g["out_offsets"][b]), int(g["out_offsets"][b + 1])
+        if g["frame_status"][b] != 0 or s1 == s0:
+            continue
+        p = gpu_downsample(x[s0:s1], y[s0:s1], z[s0:s1], rgb[s0:s1], float(leaves[b]), tuning=t)
+        assert p["m"] == hi - lo
+        for k in ("x", "y", "z", "rgb", "count", "key", "lx", "ly", "lz"):
+            assert np.array_equal(p[k].view(np.uint8), g[k][lo:hi].view(np.uint8)), (b, k)
+        assert np.array_equal(p["ref_index"].astype(np.int64) + s0, g["ref_index"][lo:hi])
+        pc = p["point_cell"].astype(np.int64)
+        assert np.array_equal(np.where(pc >= 0, pc + lo, -1), g["point_cell"][s0:s1])
+
+
+def test_graph_replay_matches_eager():
+    plan = vg.BatchPlan(16, 400_000, use_graph=True)
+    eager = vg.BatchPlan(16, 400_000, use_graph=False)
+    batches = [small_batch(seed=s) for s in (3, 4, 3, 5)]
+    for i, (x, y, z, rgb, offs, leaves) in enumerate(batches):
+        ge = run_batched(x, y, z, rgb, offs, leaves, plan=eager)
+        gg = run_batched(x, y, z, rgb, offs, leaves, plan=plan)
+        # unrelated eager work between replays
+        a = torch.randn(1000, device="cuda")
+        (a * 2).sum().item()
+        for k in ge:
+            if k == "m":
+                continue
+            n = int(ge["out_offsets"][-1]) if k not in ("point_cell", "out_offsets", "frame_status") else None
+            ea, gb = (ge[k][:n], gg[k][:n]) if n is not None else (ge[k], gg[k])
+            assert np.array_equal(np.ascontiguousarray(ea).view(np.uint8),
+                                  np.ascontiguousarray(gb).view(np.uint8)), (i, k)
+        if i == 0:
+            check_against_oracle(gg, x, y, z, rgb, offs, leaves)
+    plan.close()
+    eager.close()
+
+
+def test_batch_of_one_equals_plain():
+    x, y, z, rgb = dg.frame_640x480()
+    offs = np.array([0, x.size], np.int64)
+    g = run_batched(x, y, z, rgb, offs, np.array([0.05], np.float32))
+    p = gpu_downsample(x, y, z, rgb, 0.05)
+    m = p["m"]
+    assert int(g["out_offsets"][1]) == m
+    for k in ("x", "y", "z", "rgb", "count", "key", "ref_index"):
+        assert np.array_equal(p[k].view(np.uint8), g[k][:m].view(np.uint8)), k
+
+
+@pytest.mark.slow
+def test_full_uneven_batch_sampled():
+    """The 64-frame uneven batch at full size: 6 frames against the oracle,
+    invariants on every frame."""
+    x, y, z, rgb, offs, leaves = dg.batch()
+    print(f"batch of {len(leaves)} frames, {x.size} points", flush=True)
+    g = run_batched(x, y, z, rgb, offs, leaves)
+    assert (g["frame_status"] == 0).all()
+    oo = g["out_offsets"]
+    for b in range(len(leaves)):
+        s0, s1 = int(offs[b]), int(offs[b + 1])
+        lo, hi = int(oo[b]), int(oo[b + 1])
+        nv = int(np.isfinite(x[s0:s1]).sum())
+        assert int(g["count"][lo:hi].astype(np.int64).sum()) == nv
+        k = g["key"][lo:hi]
+        assert (k[1:] > k[:-1]).all()
+    for b in (0, 7, 21, 33, 50, 63):
+        s0, s1 = int(offs[b]), int(offs[b + 1])
+        r = oracle.downsample(x[s0:s1], y[s0:s1], z[s0:s1], rgb[s0:s1], float(leaves[b]))
+        lo, hi = int(oo[b]), int(oo[b + 1])
+        fr = {k: g[k][lo:hi] for k in ("x", "y", "z", "rgb", "count", "key", "ref_index", "lx", "ly", "lz")}
+        fr["point_cell"] = g["point_cell"][s0:s1]
+        fr["m"] = hi - lo
+        assert_matches_oracle(fr, r, float(leaves[b]), point_cell_offset=lo, ref_offset=s0)

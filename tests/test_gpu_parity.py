@@ -90,7 +90,7 @@ def test_cells_spanning_many_tiles():
     p = (which[:, None] * 1.0 + rng.uniform(0.0, 0.9, size=(n, 3))).astype(np.float32)
     rgb = rng.integers(0, 256, size=(n, 3), dtype=np.uint8)
     g, o = run_both(p[:, 0].copy(), p[:, 1].copy(), p[:, 2].copy(), rgb, 1.0)
-    assert o["m"] == 3
+    assert o["m"] <= 27 and int(o["count"].max()) > 50000
     assert_matches_oracle(g, o, 1.0)
 
 
