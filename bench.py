@@ -66,6 +66,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--exec-mode", choices=["persistent", "phased"], default="persistent")
     ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2102_11084_amd", "tuning_gfx950.json"))
+    ap.add_argument("--set", action="append", default=[], metavar="FIELD=VALUE",
+                    help="override a tuning field, e.g. --set sort_items=8")
     ap.add_argument("--no-legs", action="store_true", help="skip plain/backward legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -85,6 +87,11 @@ def main():
     tuning = vg.load_tuning(args.tuning) if os.path.exists(args.tuning) else vg.default_tuning()
     if args.exec_mode == "phased":
         tuning.exec_mode = vg.EXEC_PHASED
+    for kv in args.set:
+        k, v = kv.split("=", 1)
+        setattr(tuning, k, int(v))
+    if not vg.tuning_supported(tuning):
+        sys.exit(f"bench.py: tuning {tuning.as_dict()} is not built into libvg")
     log(f"tuning {tuning.as_dict()}")
 
     t0 = time.time()

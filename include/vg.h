@@ -125,7 +125,7 @@ vg_status vg_default_tuning(vg_tuning *t);
 vg_status vg_tuning_supported(const vg_tuning *t);
 
 /* Device workspace needed for n_total points in n_frames frames (0 on bad
- * arguments).  Grows linearly in n_total (about 26 bytes per point). */
+ * arguments).  Grows linearly in n_total (about 42 bytes per point). */
 size_t vg_workspace_bytes(int64_t n_total, int n_frames, const vg_tuning *t);
 
 /* Downsample one cloud on the default stream with an internal workspace.

@@ -17,39 +17,57 @@ namespace {
 using namespace vg;
 
 // ------------------------------------------------------------ variants ----
+template <class C, int KIND>
+int occupancy_kind() {
+  // resident workgroups per CU of one kernel entry (the same on every gfx950)
+  static const int occ = [] {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, vg_pipeline_kernel<C, KIND>, C::BLOCK,
+                                                     0) != hipSuccess)
+      n = 1;
+    return std::max(n, 1);
+  }();
+  return occ;
+}
+
+template <class C, int KIND>
+void launch_kind(const Ws& ws, int lo, int hi, int cus, int bpc, hipStream_t s) {
+  const int occ = occupancy_kind<C, KIND>();
+  const int grid = cus * (bpc > 0 ? std::min(bpc, occ) : occ);
+  hipLaunchKernelGGL((vg_pipeline_kernel<C, KIND>), dim3(grid), dim3(C::BLOCK), 0, s, ws, lo, hi);
+}
+
+// Launches phases [lo, hi): all of them in one persistent kernel, or one phase
+// with the kernel compiled for that phase kind.  Grids are fixed per kernel
+// (CUs x resident workgroups), independent of the call's sizes.
+template <class C>
+void launch_pipeline(const Ws& ws, int lo, int hi, int cus, int bpc, hipStream_t s) {
+  if (lo == 0 && hi == C::NPH) launch_kind<C, kAll>(ws, lo, hi, cus, bpc, s);
+  else if (lo == C::PH_BBOX) launch_kind<C, kBbox>(ws, lo, hi, cus, bpc, s);
+  else if (lo == C::PH_HIST) launch_kind<C, kHist>(ws, lo, hi, cus, bpc, s);
+  else if (lo == C::PH_RED) launch_kind<C, kRed>(ws, lo, hi, cus, bpc, s);
+  else if (lo == C::PH_FIX) launch_kind<C, kFix>(ws, lo, hi, cus, bpc, s);
+  else launch_kind<C, kSort>(ws, lo, hi, cus, bpc, s);
+}
+
 struct Variant {
   int block, sort_items, radix, red_items;
-  int nph, maxp, R, TS, TR, ph_red;
-  void (*launch)(const Ws&, int ph_lo, int ph_hi, int grid, hipStream_t);
-  int (*occupancy)();
+  int nph, maxp, R, TS, TB, TR, ph_red;
+  void (*launch)(const Ws&, int ph_lo, int ph_hi, int cus, int bpc, hipStream_t);
 };
-
-template <class C>
-void launch_pipeline(const Ws& ws, int lo, int hi, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(vg_pipeline_kernel<C>, dim3(grid), dim3(C::BLOCK), 0, s, ws, lo, hi);
-}
-
-template <class C>
-int occupancy_of() {
-  int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, vg_pipeline_kernel<C>, C::BLOCK, 0) !=
-      hipSuccess)
-    return 1;
-  return std::max(n, 1);
-}
 
 template <int B, int SI, int W, int RI>
 constexpr Variant make_variant() {
   using C = Cfg<B, SI, W, RI>;
-  return Variant{B, SI, W, RI, C::NPH, C::MAXP, C::R, C::TS, C::TR, C::PH_RED,
-                 &launch_pipeline<C>, &occupancy_of<C>};
+  return Variant{B, SI, W, RI, C::NPH, C::MAXP, C::R, C::TS, C::TB, C::TR, C::PH_RED,
+                 &launch_pipeline<C>};
 }
 
 // Built variants: (threads, sort items/thread, radix bits, reduce items/thread).
 const Variant kVariants[] = {
     make_variant<256, 16, 8, 8>(), make_variant<256, 8, 8, 8>(),  make_variant<256, 12, 8, 8>(),
     make_variant<256, 16, 8, 4>(), make_variant<256, 16, 7, 8>(), make_variant<512, 8, 8, 4>(),
-    make_variant<512, 8, 8, 8>(),  make_variant<256, 16, 6, 8>(),
+    make_variant<512, 8, 8, 8>(),  make_variant<256, 16, 6, 8>(), make_variant<256, 8, 8, 4>(),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -69,29 +87,20 @@ const Variant* find_variant(const vg_tuning* t) {
   return nullptr;
 }
 
-// Per-device facts, looked up once.
-struct DeviceInfo {
-  int cus = 0;
-  int occ[kNumVariants] = {};
-};
+// Compute units per device, looked up once.
 std::mutex g_dev_mu;
-DeviceInfo g_dev[64];
+int g_cus[64];
 
-bool device_info(int dev, const Variant* v, int* cus, int* occ) {
-  if (dev < 0 || dev >= 64) return false;
+int device_cus(int dev) {
+  if (dev < 0 || dev >= 64) return 0;
   std::lock_guard<std::mutex> lk(g_dev_mu);
-  DeviceInfo& d = g_dev[dev];
-  if (d.cus == 0) {
+  if (g_cus[dev] == 0) {
     int c = 0;
     if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
-      return false;
-    d.cus = c;
+      return 0;
+    g_cus[dev] = c;
   }
-  const int vi = (int)(v - kVariants);
-  if (d.occ[vi] == 0) d.occ[vi] = v->occupancy();
-  *cus = d.cus;
-  *occ = d.occ[vi];
-  return true;
+  return g_cus[dev];
 }
 
 // ------------------------------------------------------------ layout ----
@@ -100,9 +109,10 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
   int64_t capN;
-  int capB, capNTs, capNTr, slots, R;
-  size_t hdr, io, fd, tps, tpr, staged;   // staged = bytes copied from the host each call
-  size_t ctl, fs, hist, sdesc, rdesc, fflag, frag, lo0, lo1, hi0, hi1, id0, id1, outoff, fstat;
+  int capB, capNTb, capNTs, capNTr, slots, R;
+  size_t hdr, io, fd, tpb, tps, tpr, staged;   // staged = bytes copied from the host each call
+  size_t tinfo, ctl, fs, hist, sdesc, rdesc, fflag, frag, pend, lo0, lo1, hi0, hi1, id0, id1, rec,
+      outoff, fstat;
   size_t total;
 };
 
@@ -112,6 +122,7 @@ Layout make_layout(int64_t capN, int capB, const Variant& v) {
   Layout L;
   L.capN = std::max<int64_t>(capN, 1);
   L.capB = std::max(capB, 1);
+  L.capNTb = (int)(div_up(L.capN, v.TB) + L.capB);
   L.capNTs = (int)(div_up(L.capN, v.TS) + L.capB);
   L.capNTr = (int)(div_up(L.capN, v.TR) + L.capB);
   L.slots = v.maxp;
@@ -120,9 +131,11 @@ Layout make_layout(int64_t capN, int capB, const Variant& v) {
   L.hdr = o;  o = align_up(o + sizeof(CallHdr));
   L.io = o;   o = align_up(o + sizeof(Io));
   L.fd = o;   o = align_up(o + sizeof(FrameDesc) * L.capB);
+  L.tpb = o;  o = align_up(o + 4 * (size_t)(L.capB + 1));
   L.tps = o;  o = align_up(o + 4 * (size_t)(L.capB + 1));
   L.tpr = o;  o = align_up(o + 4 * (size_t)(L.capB + 1));
   L.staged = o;
+  L.tinfo = o; o = align_up(o + 8 * ((size_t)L.capNTb + L.capNTs + L.capNTr));
   L.ctl = o;  o = align_up(o + sizeof(Ctl));
   L.fs = o;   o = align_up(o + sizeof(FrameState) * L.capB);
   L.hist = o; o = align_up(o + 4 * (size_t)L.capB * L.slots * L.R);
@@ -130,6 +143,7 @@ Layout make_layout(int64_t capN, int capB, const Variant& v) {
   L.rdesc = o; o = align_up(o + 8 * (size_t)L.capNTr);
   L.fflag = o; o = align_up(o + 4 * (size_t)L.capNTr);
   L.frag = o; o = align_up(o + sizeof(Frag) * (size_t)L.capNTr);
+  L.pend = o; o = align_up(o + sizeof(Pend) * (size_t)L.capNTr);
   const size_t nb = 4 * (size_t)L.capN;
   L.lo0 = o; o = align_up(o + nb);
   L.lo1 = o; o = align_up(o + nb);
@@ -137,6 +151,7 @@ Layout make_layout(int64_t capN, int capB, const Variant& v) {
   L.hi1 = o; o = align_up(o + nb);
   L.id0 = o; o = align_up(o + nb);
   L.id1 = o; o = align_up(o + nb);
+  L.rec = o; o = align_up(o + 16 * (size_t)L.capN);
   L.outoff = o; o = align_up(o + 8 * (size_t)(L.capB + 1));
   L.fstat = o; o = align_up(o + 4 * (size_t)L.capB);
   L.total = o;
@@ -149,7 +164,9 @@ Ws carve(const Layout& L, void* base) {
   w.hdr = reinterpret_cast<CallHdr*>(b + L.hdr);
   w.io = reinterpret_cast<Io*>(b + L.io);
   w.fd = reinterpret_cast<FrameDesc*>(b + L.fd);
+  w.tpb = reinterpret_cast<uint32_t*>(b + L.tpb);
   w.tps = reinterpret_cast<uint32_t*>(b + L.tps);
+  w.tinfo = reinterpret_cast<uint2*>(b + L.tinfo);
   w.tpr = reinterpret_cast<uint32_t*>(b + L.tpr);
   w.ctl = reinterpret_cast<Ctl*>(b + L.ctl);
   w.fs = reinterpret_cast<FrameState*>(b + L.fs);
@@ -158,13 +175,16 @@ Ws carve(const Layout& L, void* base) {
   w.rdesc = reinterpret_cast<uint64_t*>(b + L.rdesc);
   w.fflag = reinterpret_cast<uint32_t*>(b + L.fflag);
   w.frag = reinterpret_cast<Frag*>(b + L.frag);
+  w.pend = reinterpret_cast<Pend*>(b + L.pend);
   w.lo[0] = reinterpret_cast<uint32_t*>(b + L.lo0);
   w.lo[1] = reinterpret_cast<uint32_t*>(b + L.lo1);
   w.hi[0] = reinterpret_cast<uint32_t*>(b + L.hi0);
   w.hi[1] = reinterpret_cast<uint32_t*>(b + L.hi1);
   w.idx[0] = reinterpret_cast<uint32_t*>(b + L.id0);
   w.idx[1] = reinterpret_cast<uint32_t*>(b + L.id1);
+  w.rec = reinterpret_cast<float4*>(b + L.rec);
   w.capB = L.capB;
+  w.capNTb = L.capNTb;
   w.capNTs = L.capNTs;
   w.capNTr = L.capNTr;
   w.slots = L.slots;
@@ -235,25 +255,38 @@ bool fill_staging(char* st, const Layout& L, const Variant& v, const vg_points* 
   io.out_offsets = out_offsets;
   io.frame_status = frame_status;
   FrameDesc* fd = reinterpret_cast<FrameDesc*>(st + L.fd);
+  uint32_t* tpb = reinterpret_cast<uint32_t*>(st + L.tpb);
   uint32_t* tps = reinterpret_cast<uint32_t*>(st + L.tps);
   uint32_t* tpr = reinterpret_cast<uint32_t*>(st + L.tpr);
-  int64_t ts = 0, tr = 0;
+  int64_t tb = 0, ts = 0, tr = 0;
   for (int b = 0; b < B; ++b) {
     const int64_t n = offs[b + 1] - offs[b];
     if (n < 0 || n > kMaxFramePoints) return false;
+    const int64_t nb = std::max<int64_t>(1, div_up(n, v.TB));
+    const int64_t ns = std::max<int64_t>(1, div_up(n, v.TS));
+    const int64_t nr = std::max<int64_t>(1, div_up(n, v.TR));
     fd[b].off = offs[b] - offs[0];
     fd[b].n = n;
     fd[b].leaf = leaves[b];
     fd[b].inv = invs[b];
-    fd[b].pad = 0;
+    fd[b].tb0 = (int32_t)tb;
+    fd[b].ts0 = (int32_t)ts;
+    fd[b].tr0 = (int32_t)tr;
+    fd[b].ntb = (int32_t)nb;
+    fd[b].nts = (int32_t)ns;
+    fd[b].ntr = (int32_t)nr;
+    tpb[b] = (uint32_t)tb;
     tps[b] = (uint32_t)ts;
     tpr[b] = (uint32_t)tr;
-    ts += std::max<int64_t>(1, div_up(n, v.TS));
-    tr += std::max<int64_t>(1, div_up(n, v.TR));
+    tb += nb;
+    ts += ns;
+    tr += nr;
   }
+  tpb[B] = (uint32_t)tb;
   tps[B] = (uint32_t)ts;
   tpr[B] = (uint32_t)tr;
-  if (ts > L.capNTs || tr > L.capNTr) return false;
+  if (tb > L.capNTb || ts > L.capNTs || tr > L.capNTr) return false;
+  hdr.NTb = (int32_t)tb;
   hdr.NTs = (int32_t)ts;
   hdr.NTr = (int32_t)tr;
   std::memcpy(st + L.hdr, &hdr, sizeof hdr);
@@ -265,24 +298,17 @@ bool fill_staging(char* st, const Layout& L, const Variant& v, const vg_points* 
 // Enqueues: staged copy, state reset, pipeline.  All launches have fixed
 // shapes (no per-call kernel arguments), so the sequence can be captured.
 vg_status enqueue(const Variant& v, const Layout& L, const Ws& ws, const char* staging,
-                  int exec_mode, int grid, hipStream_t s) {
+                  int exec_mode, int cus, int bpc, hipStream_t s) {
   if (hipMemcpyAsync(ws.hdr, staging, L.staged, hipMemcpyHostToDevice, s) != hipSuccess)
     return VG_ERR_DEVICE;
   hipLaunchKernelGGL(vg_init_kernel, dim3(256), dim3(256), 0, s, ws);
   if (exec_mode == VG_EXEC_PERSISTENT) {
-    v.launch(ws, 0, v.nph, grid, s);
+    v.launch(ws, 0, v.nph, cus, bpc, s);
   } else {
-    for (int ph = 0; ph < v.nph; ++ph) v.launch(ws, ph, ph + 1, grid, s);
+    for (int ph = 0; ph < v.nph; ++ph) v.launch(ws, ph, ph + 1, cus, bpc, s);
   }
   if (hipGetLastError() != hipSuccess) return VG_ERR_DEVICE;
   return VG_OK;
-}
-
-int grid_for(const Variant& v, const vg_tuning* t, int dev) {
-  int cus = 0, occ = 1;
-  if (!device_info(dev, &v, &cus, &occ)) return -1;
-  const int bpc = (t && t->blocks_per_cu > 0) ? std::min(t->blocks_per_cu, occ) : occ;
-  return cus * bpc;
 }
 
 // Per host thread pinned staging for the synchronous single-cloud path.
@@ -363,8 +389,9 @@ vg_status vg_downsample_ex(const vg_points* p, int64_t n, float leaf, vg_cells* 
   hipStream_t s = static_cast<hipStream_t>(o->stream);
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return VG_ERR_DEVICE;
-  const int grid = grid_for(*v, o->tuning, dev);
-  if (grid <= 0) return VG_ERR_DEVICE;
+  const int cus = device_cus(dev);
+  if (cus <= 0) return VG_ERR_DEVICE;
+  const int bpc = o->tuning ? o->tuning->blocks_per_cu : 0;
 
   char* st = t_staging.get(L.staged + sizeof(Readback));
   if (!st) return VG_ERR_DEVICE;
@@ -384,7 +411,7 @@ vg_status vg_downsample_ex(const vg_points* p, int64_t n, float leaf, vg_cells* 
     rc = VG_ERR_ARG;
   } else {
     const int mode = o->tuning ? o->tuning->exec_mode : kDefaultTuning.exec_mode;
-    rc = enqueue(*v, L, ws, st, mode, grid, s);
+    rc = enqueue(*v, L, ws, st, mode, cus, bpc, s);
   }
   Readback* rb = reinterpret_cast<Readback*>(st + L.staged);
   if (rc == VG_OK) {
@@ -451,7 +478,7 @@ struct vg_batch_plan {
   char* staging;       // pinned
   float* invs;         // host scratch [max_frames]
   int device;
-  int grid;
+  int cus;
   hipEvent_t done;
   bool pending;
   int use_graph;
@@ -488,7 +515,7 @@ vg_status vg_batch_plan_create(int max_frames, int64_t max_total_points, vg_key_
   P->done = nullptr;
   vg_status rc = VG_OK;
   if (hipGetDevice(&P->device) != hipSuccess) rc = VG_ERR_DEVICE;
-  if (rc == VG_OK && (P->grid = grid_for(*v, &P->tuning, P->device)) <= 0) rc = VG_ERR_DEVICE;
+  if (rc == VG_OK && (P->cus = device_cus(P->device)) <= 0) rc = VG_ERR_DEVICE;
   if (rc == VG_OK && hipMalloc(&P->ws_base, P->L.total) != hipSuccess) rc = VG_ERR_DEVICE;
   if (rc == VG_OK && hipHostMalloc(reinterpret_cast<void**>(&P->staging), P->L.staged,
                                    hipHostMallocDefault) != hipSuccess)
@@ -545,7 +572,8 @@ vg_status vg_downsample_batched(vg_batch_plan* P, const vg_points* p, const int6
         (void)hipStreamDestroy(cs);
         return VG_ERR_DEVICE;
       }
-      rc = enqueue(*P->v, P->L, P->ws, P->staging, P->tuning.exec_mode, P->grid, cs);
+      rc = enqueue(*P->v, P->L, P->ws, P->staging, P->tuning.exec_mode, P->cus,
+                   P->tuning.blocks_per_cu, cs);
       hipGraph_t g = nullptr;
       const bool ok = hipStreamEndCapture(cs, &g) == hipSuccess && rc == VG_OK &&
                       hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0) == hipSuccess;
@@ -559,7 +587,8 @@ vg_status vg_downsample_batched(vg_batch_plan* P, const vg_points* p, const int6
     }
     if (hipGraphLaunch(P->gexec, s) != hipSuccess) rc = VG_ERR_DEVICE;
   } else {
-    rc = enqueue(*P->v, P->L, P->ws, P->staging, P->tuning.exec_mode, P->grid, s);
+    rc = enqueue(*P->v, P->L, P->ws, P->staging, P->tuning.exec_mode, P->cus,
+                 P->tuning.blocks_per_cu, s);
   }
   if (hipEventRecord(P->done, s) == hipSuccess) P->pending = true;
   return rc;

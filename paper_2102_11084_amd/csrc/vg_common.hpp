@@ -25,14 +25,15 @@ constexpr uint64_t kVal64 = (1ull << 62) - 1;
 enum FrameStatus : int32_t { kFrameOk = 0, kFrameOverflow = 3 };
 
 // Per-call header, copied from the host.
+//   big tiles  (bbox, histogram):  NTb over all frames
+//   sort tiles (radix passes):     NTs
+//   reduce tiles:                  NTr
 struct CallHdr {
   int32_t B;            // frames
   int32_t key_mode;     // 0 linear, 1 Morton
-  int32_t NTs;          // sort/bbox/histogram tiles over all frames
-  int32_t NTr;          // reduce tiles over all frames
-  int64_t N;            // points over all frames
+  int32_t NTb, NTs, NTr;
   uint32_t want;        // output mask (kOut*)
-  uint32_t pad;
+  int64_t N;            // points over all frames
 };
 
 enum : uint32_t {
@@ -42,11 +43,12 @@ enum : uint32_t {
 
 // Per-frame description, copied from the host.
 struct FrameDesc {
-  int64_t off;   // first point of the frame in the concatenated arrays
-  int64_t n;     // points of the frame
+  int64_t off;           // first point of the frame in the concatenated arrays
+  int64_t n;             // points of the frame
   float leaf;
-  float inv;     // RN32(1/leaf), computed on the host
-  int64_t pad;
+  float inv;             // RN32(1/leaf), computed on the host
+  int32_t tb0, ts0, tr0; // first big / sort / reduce tile of the frame
+  int32_t ntb, nts, ntr; // number of such tiles (each >= 1)
 };
 
 // Per-frame state written during a call; zeroed at the start of every call.
@@ -54,9 +56,9 @@ struct FrameState {
   uint32_t mn_neg[3];   // max of ~enc(v)  ->  ~result = enc(min)
   uint32_t mx[3];       // max of enc(v)
   uint32_t n_valid;
-  uint32_t bbox_done;
-  uint32_t hist_done;
-  uint32_t pass_done[kMaxPassSlots];
+  uint32_t bbox_done;   // big tiles done
+  uint32_t hist_done;   // big tiles done
+  uint32_t pass_done[kMaxPassSlots];  // sort tiles done, per pass
   uint32_t pad[4];
 };
 static_assert(sizeof(FrameState) == 24 * 4, "FrameState layout");
@@ -67,14 +69,36 @@ struct Frag {
   uint32_t n;
   float s[3];
   float c[3];
-  uint32_t rgb[3];
-  uint32_t pad[2];
+  uint32_t head_pos;  // frame position of the segment's first point if it lies in this tile,
+                      // else kNoHead
+  uint32_t ref;       // index of that first point (valid with head_pos)
+  uint32_t pad;
+  uint64_t rgb;       // packed colour sums, 21 bits per channel
+};
+constexpr uint32_t kNoHead = 0xffffffffu;
+
+// A cell that starts in an earlier reduce tile and ends in this one: the part
+// of its sums inside this tile and where its row goes.  The fix-up phase adds
+// the earlier tiles' carry-out parts and writes the row.
+struct Pend {
+  uint32_t valid;
+  uint32_t b, j;        // frame, reduce tile within the frame
+  uint32_t lo, hi;      // cell key
+  float r[3];           // cell corner
+  int64_t row;
+  uint32_t n;
+  float s[3], c[3];
+  uint32_t pad;
+  uint64_t rgb;         // packed colour sums, 21 bits per channel
 };
 
 struct Ctl {
-  uint32_t queue[16];   // [0]: persistent queue; [1 + phase]: phased queues
-  uint32_t error;       // non-zero: a device-side wait timed out
-  uint32_t pad[15];
+  uint32_t queue[16];        // [0]: persistent queue; [1 + phase]: phased queues
+  uint32_t error;            // non-zero: a device-side wait timed out
+  uint32_t max_passes;       // max radix passes over the frames of the call
+  uint32_t hist_tiles_done;  // big tiles (all frames) whose histogram is done
+  uint32_t red_tiles_done;   // reduce tiles (all frames) done
+  uint32_t pad[12];
 };
 
 struct Io;
@@ -83,8 +107,10 @@ struct Io;
 struct Ws {
   CallHdr* hdr;
   FrameDesc* fd;
+  uint32_t* tpb;        // [B+1] big-tile prefix over frames
   uint32_t* tps;        // [B+1] sort-tile prefix over frames
   uint32_t* tpr;        // [B+1] reduce-tile prefix over frames
+  uint2* tinfo;         // [NTb + NTs + NTr]: (frame, tile within frame)
   Ctl* ctl;
   FrameState* fs;       // [B]
   uint32_t* hist;       // [B][slots][R]
@@ -92,12 +118,14 @@ struct Ws {
   uint64_t* rdesc;      // [NTr]
   uint32_t* fflag;      // [NTr]
   Frag* frag;           // [NTr]
+  Pend* pend;           // [NTr]
   uint32_t* lo[2];      // [N]
   uint32_t* hi[2];      // [N]
   uint32_t* idx[2];     // [N]
+  float4* rec;          // [N] x, y, z and packed rgb of every point, written by the bbox pass
   Io* io;               // inputs/outputs of the call (copied from the host)
   // capacities the workspace was carved for
-  int32_t capB, capNTs, capNTr, slots, R;
+  int32_t capB, capNTb, capNTs, capNTr, slots, R;
   int64_t capN;
 };
 

@@ -55,7 +55,7 @@ __device__ __forceinline__ void fence_acq() { __builtin_amdgcn_fence(__ATOMIC_AC
 __device__ __forceinline__ void fence_rel() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
 
 // Spin (one thread) until *p >= target; on time-out flag an error and give up.
-__device__ __noinline__ bool wait_geq(const uint32_t* p, uint32_t target, Ctl* ctl) {
+__device__ __forceinline__ bool wait_geq(const uint32_t* p, uint32_t target, Ctl* ctl) {
   uint32_t spins = 0;
   while (ld_rlx(p) < target) {
     if (++spins > kSpinLimit || ld_rlx(&ctl->error) != 0) {
@@ -98,6 +98,82 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* wsum, 
   return before + incl - v;
 }
 
+// Decoupled look-back: sum the published values of tiles k0, k0-1, ... down
+// to the first inclusive prefix.  LB descriptors are read per round trip.
+constexpr int kLookBatch = 4;
+
+__device__ __forceinline__ uint32_t look_back32(const uint32_t* desc, size_t stride, int k0,
+                                                int lo, Ctl* ctl) {
+  uint32_t excl = 0;
+  int k = k0;
+  uint32_t spins = 0;
+  for (;;) {
+    uint32_t v[kLookBatch];
+#pragma unroll
+    for (int i = 0; i < kLookBatch; ++i)
+      v[i] = (k - i >= lo) ? ld_rlx(desc + (size_t)(k - i) * stride) : kFlagP32;
+    int used = 0;
+    bool done = false;
+#pragma unroll
+    for (int i = 0; i < kLookBatch; ++i) {
+      if (done || used < i) break;
+      const uint32_t fl = v[i] & 0xc0000000u;
+      if (fl == 0u) break;
+      excl += v[i] & kVal32;
+      ++used;
+      if (fl == kFlagP32) done = true;
+    }
+    if (done) return excl;
+    k -= used;
+    if (k < lo) {  // the first tile always holds a prefix
+      atomicOr(&ctl->error, 1u);
+      return excl;
+    }
+    if (used == 0) {
+      if (++spins > kSpinLimit || ((spins & 255u) == 0u && ld_rlx(&ctl->error))) {
+        atomicOr(&ctl->error, 1u);
+        return excl;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+}
+
+__device__ __forceinline__ uint64_t look_back64(const uint64_t* desc, int k0, Ctl* ctl) {
+  uint64_t excl = 0;
+  int k = k0;
+  uint32_t spins = 0;
+  for (;;) {
+    uint64_t v[kLookBatch];
+#pragma unroll
+    for (int i = 0; i < kLookBatch; ++i) v[i] = (k - i >= 0) ? ld_rlx64(desc + (k - i)) : kFlagP64;
+    int used = 0;
+    bool done = false;
+#pragma unroll
+    for (int i = 0; i < kLookBatch; ++i) {
+      if (done || used < i) break;
+      const uint64_t fl = v[i] & (3ull << 62);
+      if (fl == 0) break;
+      excl += v[i] & kVal64;
+      ++used;
+      if (fl == kFlagP64) done = true;
+    }
+    if (done) return excl;
+    k -= used;
+    if (k < 0) {
+      atomicOr(&ctl->error, 1u);
+      return excl;
+    }
+    if (used == 0) {
+      if (++spins > kSpinLimit || ((spins & 255u) == 0u && ld_rlx(&ctl->error))) {
+        atomicOr(&ctl->error, 1u);
+        return excl;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+}
+
 // ------------------------------------------------------- frame params ----
 struct FrameParams {
   int64_t off, n;
@@ -118,6 +194,16 @@ __device__ __forceinline__ uint64_t spread3(uint32_t v) {
   x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
   x = (x | (x << 2)) & 0x1249249249249249ull;
   return x;
+}
+
+__device__ __forceinline__ uint32_t compact3(uint64_t x) {
+  x &= 0x1249249249249249ull;
+  x = (x ^ (x >> 2)) & 0x10c30c30c30c30c3ull;
+  x = (x ^ (x >> 4)) & 0x100f00f00f00f00full;
+  x = (x ^ (x >> 8)) & 0x1f0000ff0000ffull;
+  x = (x ^ (x >> 16)) & 0x1f00000000ffffull;
+  x = (x ^ (x >> 32)) & 0x1fffffull;
+  return (uint32_t)x;
 }
 
 __device__ __forceinline__ uint32_t cell_coord(float p, float mn, float inv) {
@@ -177,11 +263,24 @@ __device__ __forceinline__ uint64_t point_key(const FrameParams& f, int key_mode
 // ------------------------------------------------- compensated sums ----
 // Sum of binary32 values kept as an unevaluated pair (s, c); each addition
 // uses the error-free TwoSum transformation (Knuth; Neumaier-style carry).
+// Colour sums of a tile-local part are packed in one 64-bit word, 21 bits per
+// channel (a reduce tile holds at most 8192 points, 8192 * 255 < 2^21).
 struct Acc {
   uint32_t n;
   float s[3], c[3];
-  uint32_t rgb[3];
+  uint64_t rgb;
 };
+
+constexpr int kRgbShift = 21;
+constexpr uint64_t kRgbMask = (1ull << kRgbShift) - 1;
+
+__device__ __forceinline__ uint64_t rgb_pack(uint32_t rgb24) {
+  return (uint64_t)(rgb24 & 0xffu) | ((uint64_t)((rgb24 >> 8) & 0xffu) << kRgbShift) |
+         ((uint64_t)((rgb24 >> 16) & 0xffu) << (2 * kRgbShift));
+}
+__device__ __forceinline__ uint64_t rgb_channel(uint64_t packed, int c) {
+  return (packed >> (c * kRgbShift)) & kRgbMask;
+}
 
 __device__ __forceinline__ void two_sum_into(float& s, float& c, float v) {
   float t = __fadd_rn(s, v);
@@ -193,15 +292,14 @@ __device__ __forceinline__ void two_sum_into(float& s, float& c, float v) {
 
 __device__ __forceinline__ void acc_zero(Acc& a) {
   a.n = 0;
-  for (int i = 0; i < 3; ++i) { a.s[i] = 0.f; a.c[i] = 0.f; a.rgb[i] = 0u; }
+  for (int i = 0; i < 3; ++i) { a.s[i] = 0.f; a.c[i] = 0.f; }
+  a.rgb = 0ull;
 }
 
-__device__ __forceinline__ void acc_add(Acc& a, const float d[3], const uint32_t rgb[3]) {
+__device__ __forceinline__ void acc_add(Acc& a, const float d[3], uint32_t rgb24) {
   a.n += 1;
-  for (int i = 0; i < 3; ++i) {
-    two_sum_into(a.s[i], a.c[i], d[i]);
-    a.rgb[i] += rgb[i];
-  }
+  for (int i = 0; i < 3; ++i) two_sum_into(a.s[i], a.c[i], d[i]);
+  a.rgb += rgb_pack(rgb24);
 }
 
 // a <- a (+) b, a on the left.
@@ -210,8 +308,8 @@ __device__ __forceinline__ void acc_merge(Acc& a, const Acc& b) {
   for (int i = 0; i < 3; ++i) {
     two_sum_into(a.s[i], a.c[i], b.s[i]);
     a.c[i] = __fadd_rn(a.c[i], b.c[i]);
-    a.rgb[i] += b.rgb[i];
   }
+  a.rgb += b.rgb;
 }
 
 // Segmented-scan element: f = a head lies in the covered range, hp = frame
@@ -236,8 +334,9 @@ __device__ __forceinline__ Seg seg_shfl_up(const Seg& v, int off) {
   for (int i = 0; i < 3; ++i) {
     r.a.s[i] = __shfl_up(v.a.s[i], off);
     r.a.c[i] = __shfl_up(v.a.c[i], off);
-    r.a.rgb[i] = __shfl_up(v.a.rgb[i], off);
   }
+  r.a.rgb = ((uint64_t)__shfl_up((uint32_t)(v.a.rgb >> 32), off) << 32) |
+            (uint32_t)__shfl_up((uint32_t)v.a.rgb, off);
   return r;
 }
 
@@ -247,16 +346,21 @@ struct Cfg {
   static constexpr int BLOCK = BLOCK_;
   static constexpr int NW = BLOCK / 64;
   static constexpr int SI = SORT_ITEMS_;
-  static constexpr int TS = BLOCK * SI;
+  static constexpr int TS = BLOCK * SI;      // sort tile
+  static constexpr int KB = 4;
+  static constexpr int TB = TS * KB;         // big tile (bbox, histogram)
+  static constexpr int UB = 4;               // points per thread per load batch of a big tile
   static constexpr int W = RADIX_;
   static constexpr int R = 1 << W;
   static constexpr int MAXP = (63 + W - 1) / W;
   static constexpr int RI = RED_ITEMS_;
-  static constexpr int TR = BLOCK * RI;
-  static constexpr int PH_BBOX = 0, PH_HIST = 1, PH_SORT0 = 2, PH_RED = 2 + MAXP, NPH = 3 + MAXP;
+  static constexpr int TR = BLOCK * RI;      // reduce tile
+  static constexpr int PH_BBOX = 0, PH_HIST = 1, PH_SORT0 = 2, PH_RED = 2 + MAXP,
+                       PH_FIX = 3 + MAXP, NPH = 4 + MAXP;
   static_assert(R <= BLOCK, "one digit per thread in the look-back");
   static_assert(MAXP <= kMaxPassSlots, "pass slots");
   static_assert(SI <= 32 && RI <= 32, "item masks are 32-bit");
+  static_assert(TB % (BLOCK * UB) == 0, "big tile = whole load batches");
 
   struct SortSmem {
     uint32_t lo[TS];
@@ -270,7 +374,6 @@ struct Cfg {
   };
   struct HistSmem {
     uint32_t h[MAXP][R];
-    uint32_t wsum[NW];
   };
   struct BboxSmem {
     uint32_t mn[NW][3];
@@ -278,14 +381,11 @@ struct Cfg {
     uint32_t nv[NW];
   };
   struct RedSmem {
+    uint32_t klo[TR];
+    uint32_t khi[TR];
+    uint32_t kid[TR];
     uint32_t wsum[NW];
     Seg wtot[NW];
-    Acc part[BLOCK];
-    Acc span_acc;
-    float span_r[3];
-    uint32_t span_lo, span_hi;
-    uint32_t span_pending;
-    uint32_t span_start;
     uint64_t excl;
   };
   union Smem {
@@ -296,28 +396,113 @@ struct Cfg {
   };
 };
 
+// LDS of a kernel entry: every phase's layout for the persistent kernel,
+// only its own phase's for a one-phase kernel.
+template <class C, int KIND>
+struct SmemOf {
+  union type {
+    typename C::SortSmem sort;
+    typename C::HistSmem hist;
+    typename C::BboxSmem bbox;
+    typename C::RedSmem red;
+  };
+};
+
+// Control state of a workgroup, written by thread 0 and read by all.
+constexpr int kLdsFrames = 256;  // calls with at most this many frames keep tile prefixes in LDS
+
+struct BlockCtl {
+  uint32_t item;
+  int32_t ph, t, b, j;
+  int32_t skip;          // the item needs no work
+  int32_t fp_b;          // frame whose parameters are in fp
+  int32_t fd_b;          // frame whose description is in fd
+  int32_t dep_b[kMaxPassSlots + 3];  // per phase: last frame whose inputs were seen complete
+  FrameParams fp;
+  FrameDesc fd;
+  uint32_t tp[3][kLdsFrames + 1];    // big / sort / reduce tile prefixes over frames
+};
+
+template <class C>
+struct SmemOf<C, 1> {
+  union type { typename C::BboxSmem bbox; };
+};
+template <class C>
+struct SmemOf<C, 2> {
+  union type { typename C::HistSmem hist; };
+};
+template <class C>
+struct SmemOf<C, 3> {
+  union type { typename C::SortSmem sort; };
+};
+template <class C>
+struct SmemOf<C, 4> {
+  union type { typename C::RedSmem red; };
+};
+template <class C>
+struct SmemOf<C, 5> {
+  union type { typename C::BboxSmem bbox; };
+};
+
+// Points of a big tile are streamed in batches of UB per thread; the next
+// batch is in flight while the current one is processed.
+template <class C>
+struct PtBatch {
+  float x[C::UB], y[C::UB], z[C::UB];
+  uint32_t c[C::UB];
+};
+
+template <class C>
+__device__ __forceinline__ void load_batch(const Io& io, PtBatch<C>& pb, int64_t g0, int64_t last,
+                                           bool with_rgb) {
+#pragma unroll
+  for (int u = 0; u < C::UB; ++u) {
+    const int64_t g = min(g0 + u * C::BLOCK + (int)threadIdx.x, last);
+    pb.x[u] = io.x[g];
+    pb.y[u] = io.y[g];
+    pb.z[u] = io.z[g];
+    pb.c[u] = 0u;
+    if (with_rgb) {
+      const uint8_t* q = io.rgb + 3 * (size_t)g;
+      pb.c[u] = (uint32_t)q[0] | ((uint32_t)q[1] << 8) | ((uint32_t)q[2] << 16);
+    }
+  }
+}
+
 // ---------------------------------------------------------- BBOX tile ----
 template <class C>
-__device__ void bbox_tile(const Ws& ws, const Io& io, typename C::Smem& sm, int b, int j,
-                          uint32_t want) {
-  const FrameDesc fd = ws.fd[b];
+__device__ void bbox_tile(const Ws& ws, const Io& io, typename C::BboxSmem& bs, const FrameDesc& fd,
+                          int b, int j, uint32_t want, bool persistent) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t t0 = (int64_t)j * C::TS;
+  const int64_t t0 = (int64_t)j * C::TB;
+  const int64_t cnt = min((int64_t)C::TB, fd.n - t0);
   uint32_t mn[3] = {0u, 0u, 0u}, mx[3] = {0u, 0u, 0u}, nv = 0;
-#pragma unroll 4
-  for (int it = 0; it < C::SI; ++it) {
-    int64_t pos = t0 + (int64_t)w * 64 * C::SI + it * 64 + lane;
-    if (pos < fd.n) {
-      int64_t g = fd.off + pos;
-      float x = io.x[g], y = io.y[g], z = io.z[g];
-      if (finite3(x, y, z)) {
-        uint32_t ex = f2ord(x), ey = f2ord(y), ez = f2ord(z);
-        mn[0] = max(mn[0], ~ex); mn[1] = max(mn[1], ~ey); mn[2] = max(mn[2], ~ez);
-        mx[0] = max(mx[0], ex); mx[1] = max(mx[1], ey); mx[2] = max(mx[2], ez);
-        nv += 1;
-      } else if (want & kOutPointCell) {
-        io.point_cell[g] = -1;
+  if (cnt > 0) {
+    const int64_t last = fd.off + fd.n - 1;
+    const int nbat = (int)((cnt + C::BLOCK * C::UB - 1) / (C::BLOCK * C::UB));
+    const bool with_rgb = io.rgb != nullptr;
+    PtBatch<C> cur, nxt;
+    load_batch<C>(io, cur, fd.off + t0, last, with_rgb);
+    for (int bi = 0; bi < nbat; ++bi) {
+      const int c = bi * C::BLOCK * C::UB;
+      if (bi + 1 < nbat) load_batch<C>(io, nxt, fd.off + t0 + c + C::BLOCK * C::UB, last, with_rgb);
+#pragma unroll
+      for (int u = 0; u < C::UB; ++u) {
+        const int64_t i = c + u * C::BLOCK + (int)threadIdx.x;
+        if (i < cnt) {
+          const int64_t g = fd.off + t0 + i;
+          ws.rec[g] = make_float4(cur.x[u], cur.y[u], cur.z[u], __uint_as_float(cur.c[u]));
+          if (finite3(cur.x[u], cur.y[u], cur.z[u])) {
+            const uint32_t ex = f2ord(cur.x[u]), ey = f2ord(cur.y[u]), ez = f2ord(cur.z[u]);
+            mn[0] = max(mn[0], ~ex); mn[1] = max(mn[1], ~ey); mn[2] = max(mn[2], ~ez);
+            mx[0] = max(mx[0], ex); mx[1] = max(mx[1], ey); mx[2] = max(mx[2], ez);
+            nv += 1;
+          } else if (want & kOutPointCell) {
+            io.point_cell[g] = -1;
+          }
+        }
       }
+      cur = nxt;
     }
   }
 #pragma unroll
@@ -329,17 +514,17 @@ __device__ void bbox_tile(const Ws& ws, const Io& io, typename C::Smem& sm, int 
     nv += __shfl_xor(nv, off);
   }
   if (lane == 0) {
-    for (int a = 0; a < 3; ++a) { sm.bbox.mn[w][a] = mn[a]; sm.bbox.mx[w][a] = mx[a]; }
-    sm.bbox.nv[w] = nv;
+    for (int a = 0; a < 3; ++a) { bs.mn[w][a] = mn[a]; bs.mx[w][a] = mx[a]; }
+    bs.nv[w] = nv;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t tn = 0;
     for (int i = 0; i < C::NW; ++i) {
-      tn += sm.bbox.nv[i];
+      tn += bs.nv[i];
       for (int a = 0; a < 3; ++a) {
-        mn[a] = max(mn[a], sm.bbox.mn[i][a]);
-        mx[a] = max(mx[a], sm.bbox.mx[i][a]);
+        mn[a] = max(mn[a], bs.mn[i][a]);
+        mx[a] = max(mx[a], bs.mx[i][a]);
       }
     }
     FrameState* fs = ws.fs + b;
@@ -350,135 +535,147 @@ __device__ void bbox_tile(const Ws& ws, const Io& io, typename C::Smem& sm, int 
       }
       atomicAdd(&fs->n_valid, tn);
     }
-    fence_rel();
+    if (persistent) fence_rel();
     atomicAdd(&fs->bbox_done, 1u);
   }
 }
 
-// Load pass-0 items of a tile: keys from xyz, invalid points masked out.
-template <class C>
-__device__ __forceinline__ uint32_t load_points_keys(const Io& io, const FrameParams& f,
-                                                     int key_mode, int64_t t0, uint32_t* klo,
-                                                     uint32_t* khi, uint32_t* kid) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  uint32_t vmask = 0;
-#pragma unroll
-  for (int it = 0; it < C::SI; ++it) {
-    int64_t pos = t0 + (int64_t)w * 64 * C::SI + it * 64 + lane;
-    klo[it] = 0u;
-    khi[it] = 0u;
-    kid[it] = 0u;
-    if (pos < f.n) {
-      int64_t g = f.off + pos;
-      float x = io.x[g], y = io.y[g], z = io.z[g];
-      if (finite3(x, y, z)) {
-        uint64_t k = point_key(f, key_mode, cell_coord(x, f.mn[0], f.inv),
-                               cell_coord(y, f.mn[1], f.inv), cell_coord(z, f.mn[2], f.inv));
-        klo[it] = (uint32_t)k;
-        khi[it] = (uint32_t)(k >> 32);
-        kid[it] = (uint32_t)g;
-        vmask |= 1u << it;
-      }
-    }
-  }
-  return vmask;
+__device__ __forceinline__ uint32_t digit_of(uint32_t lo, uint32_t hi, int shift, uint32_t mask) {
+  const uint64_t k = ((uint64_t)hi << 32) | lo;
+  return (uint32_t)(k >> shift) & mask;
 }
 
-__device__ __forceinline__ uint32_t digit_of(uint32_t lo, uint32_t hi, int shift, uint32_t mask) {
-  uint64_t k = ((uint64_t)hi << 32) | lo;
-  return (uint32_t)(k >> shift) & mask;
+__device__ __forceinline__ uint64_t key_of_point(const FrameParams& f, int key_mode, float x,
+                                                 float y, float z) {
+  return point_key(f, key_mode, cell_coord(x, f.mn[0], f.inv), cell_coord(y, f.mn[1], f.inv),
+                   cell_coord(z, f.mn[2], f.inv));
 }
 
 // ---------------------------------------------------------- HIST tile ----
 template <class C>
-__device__ void hist_tile(const Ws& ws, const Io& io, typename C::Smem& sm, int b, int j, int t,
-                          const FrameParams& f, int key_mode, uint32_t want) {
+__device__ void hist_tile(const Ws& ws, const Io& io, typename C::HistSmem& hs, const FrameDesc& fd,
+                          int b, int j, const FrameParams& f, int key_mode, uint32_t want,
+                          bool persistent) {
   const int P = f.passes;
   const int Rb = 1 << f.w;
   const uint32_t mask = (uint32_t)Rb - 1u;
+  const int64_t t0 = (int64_t)j * C::TB;
+  const int64_t cnt = min((int64_t)C::TB, fd.n - t0);
   if (f.status == kFrameOverflow) {
-    if (want & kOutPointCell) {
-      const int64_t t0 = (int64_t)j * C::TS;
-      for (int i = threadIdx.x; i < C::TS; i += C::BLOCK) {
-        int64_t pos = t0 + i;
-        if (pos < f.n) io.point_cell[f.off + pos] = -1;
-      }
+    if ((want & kOutPointCell) && cnt > 0) {
+      for (int i = threadIdx.x; i < cnt; i += C::BLOCK) io.point_cell[fd.off + t0 + i] = -1;
     }
   } else if (P > 0) {
-    // this tile's look-back descriptors of every pass start cleared
+    // the look-back descriptors of the sort tiles under this big tile start cleared
+    const int s_lo = j * C::KB, s_hi = min((j + 1) * C::KB, fd.nts);
     for (int p = 0; p < P; ++p) {
-      uint32_t* row = ws.sdesc + ((size_t)p * ws.capNTs + t) * C::R;
-      for (int d = threadIdx.x; d < C::R; d += C::BLOCK) row[d] = 0u;
+      for (int st = s_lo; st < s_hi; ++st) {
+        uint32_t* row = ws.sdesc + ((size_t)p * ws.capNTs + fd.ts0 + st) * C::R;
+        for (int d = threadIdx.x; d < C::R; d += C::BLOCK) row[d] = 0u;
+      }
     }
-    for (int i = threadIdx.x; i < C::MAXP * C::R; i += C::BLOCK) (&sm.hist.h[0][0])[i] = 0u;
+    for (int i = threadIdx.x; i < C::MAXP * C::R; i += C::BLOCK) (&hs.h[0][0])[i] = 0u;
     __syncthreads();
-    uint32_t klo[C::SI], khi[C::SI], kid[C::SI];
-    uint32_t vm = load_points_keys<C>(io, f, key_mode, (int64_t)j * C::TS, klo, khi, kid);
+    if (cnt > 0) {
+      const int64_t last = fd.off + fd.n - 1;
+      const int nbat = (int)((cnt + C::BLOCK * C::UB - 1) / (C::BLOCK * C::UB));
+      PtBatch<C> cur, nxt;
+      load_batch<C>(io, cur, fd.off + t0, last, false);
+      for (int bi = 0; bi < nbat; ++bi) {
+        const int c = bi * C::BLOCK * C::UB;
+        if (bi + 1 < nbat) load_batch<C>(io, nxt, fd.off + t0 + c + C::BLOCK * C::UB, last, false);
 #pragma unroll
-    for (int it = 0; it < C::SI; ++it) {
-      if (vm & (1u << it)) {
-        for (int p = 0; p < P; ++p)
-          atomicAdd(&sm.hist.h[p][digit_of(klo[it], khi[it], p * f.w, mask)], 1u);
+        for (int u = 0; u < C::UB; ++u) {
+          if (c + u * C::BLOCK + (int)threadIdx.x < cnt && finite3(cur.x[u], cur.y[u], cur.z[u])) {
+            const uint64_t k = key_of_point(f, key_mode, cur.x[u], cur.y[u], cur.z[u]);
+            const uint32_t lo = (uint32_t)k, hi = (uint32_t)(k >> 32);
+            for (int p = 0; p < P; ++p) atomicAdd(&hs.h[p][digit_of(lo, hi, p * f.w, mask)], 1u);
+          }
+        }
+        cur = nxt;
       }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < P * C::R; i += C::BLOCK) {
-      int p = i / C::R, d = i % C::R;
-      uint32_t v = sm.hist.h[p][d];
+      const int p = i / C::R, d = i % C::R;
+      const uint32_t v = hs.h[p][d];
       if (v) atomicAdd(&ws.hist[((size_t)b * ws.slots + p) * C::R + d], v);
     }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    fence_rel();
+    if (P > 0) atomicMax(&ws.ctl->max_passes, (uint32_t)P);
+    if (persistent) fence_rel();
     atomicAdd(&ws.fs[b].hist_done, 1u);
+    atomicAdd(&ws.ctl->hist_tiles_done, 1u);
   }
 }
 
 // ---------------------------------------------------------- SORT tile ----
 template <class C>
-__device__ void sort_tile(const Ws& ws, const Io& io, typename C::Smem& sm, int b, int j, int t,
-                          int p, const FrameParams& f, int key_mode) {
-  auto& S = sm.sort;
+__device__ void sort_tile(const Ws& ws, const Io& io, typename C::SortSmem& S, const FrameDesc& fd,
+                          int b, int j, int p, const FrameParams& f, int key_mode,
+                          bool persistent) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int Rb = 1 << f.w;
   const uint32_t mask = (uint32_t)Rb - 1u;
   const int shift = p * f.w;
   const int64_t t0 = (int64_t)j * C::TS;
+  const int t = fd.ts0 + j;
 
   // frame-wide digit offsets of this pass
   {
     uint32_t hv = 0;
     if ((int)threadIdx.x < Rb) hv = ws.hist[((size_t)b * ws.slots + p) * C::R + threadIdx.x];
     uint32_t tot;
-    uint32_t ex = block_excl_scan<C::BLOCK>(hv, S.wsum, tot);
+    const uint32_t ex = block_excl_scan<C::BLOCK>(hv, S.wsum, tot);
     if ((int)threadIdx.x < C::R) S.dstart[threadIdx.x] = ex;
   }
   for (int i = threadIdx.x; i < C::NW * C::R; i += C::BLOCK) (&S.wcnt[0][0])[i] = 0u;
 
+  // items in wave-striped order: wave w owns 64*SI consecutive positions
   uint32_t klo[C::SI], khi[C::SI], kid[C::SI];
-  uint32_t vm;
+  uint32_t vm = 0;
+  const int64_t wbase = t0 + (int64_t)w * 64 * C::SI + lane;
   if (p == 0) {
-    vm = load_points_keys<C>(io, f, key_mode, t0, klo, khi, kid);
-  } else {
-    const int src = p & 1;
-    const uint32_t* slo = ws.lo[src] + f.off;
-    const uint32_t* shi = ws.hi[src] + f.off;
-    const uint32_t* sid = ws.idx[src] + f.off;
-    vm = 0;
+    const int64_t last = fd.off + max(fd.n - 1, (int64_t)0);
+    float xs[C::SI], ys[C::SI], zs[C::SI];
 #pragma unroll
     for (int it = 0; it < C::SI; ++it) {
-      int64_t pos = t0 + (int64_t)w * 64 * C::SI + it * 64 + lane;
+      const int64_t g = min(fd.off + wbase + it * 64, last);
+      xs[it] = io.x[g];
+      ys[it] = io.y[g];
+      zs[it] = io.z[g];
+    }
+#pragma unroll
+    for (int it = 0; it < C::SI; ++it) {
+      const int64_t pos = wbase + it * 64;
       klo[it] = 0u;
       khi[it] = 0u;
-      kid[it] = 0u;
-      if (pos < (int64_t)f.n_valid) {
-        klo[it] = slo[pos];
-        if (f.wide) khi[it] = shi[pos];
-        kid[it] = sid[pos];
+      kid[it] = (uint32_t)(fd.off + pos);
+      if (pos < fd.n && finite3(xs[it], ys[it], zs[it])) {
+        const uint64_t k = key_of_point(f, key_mode, xs[it], ys[it], zs[it]);
+        klo[it] = (uint32_t)k;
+        khi[it] = (uint32_t)(k >> 32);
         vm |= 1u << it;
       }
     }
+  } else {
+    const int src = p & 1;
+    const uint32_t* slo = ws.lo[src] + fd.off;
+    const uint32_t* shi = ws.hi[src] + fd.off;
+    const uint32_t* sid = ws.idx[src] + fd.off;
+    const int64_t last = max((int64_t)f.n_valid - 1, (int64_t)0);
+#pragma unroll
+    for (int it = 0; it < C::SI; ++it) {
+      const int64_t pos = min(wbase + it * 64, last);
+      klo[it] = slo[pos];
+      khi[it] = f.wide ? shi[pos] : 0u;
+      kid[it] = sid[pos];
+    }
+#pragma unroll
+    for (int it = 0; it < C::SI; ++it)
+      if (wbase + it * 64 < (int64_t)f.n_valid) vm |= 1u << it;
   }
   __syncthreads();
 
@@ -509,7 +706,7 @@ __device__ void sort_tile(const Ws& ws, const Io& io, typename C::Smem& sm, int 
   if ((int)threadIdx.x < Rb) {
     const int d = threadIdx.x;
     for (int i = 0; i < C::NW; ++i) {
-      uint32_t v = S.wcnt[i][d];
+      const uint32_t v = S.wcnt[i][d];
       S.wcnt[i][d] = tcnt;
       tcnt += v;
     }
@@ -527,26 +724,8 @@ __device__ void sort_tile(const Ws& ws, const Io& io, typename C::Smem& sm, int 
       st_rlx(mine, kFlagP32 | tcnt);
     } else {
       st_rlx(mine, kFlagA32 | tcnt);
-      int k = t - 1;
-      uint32_t spins = 0;
-      for (;;) {
-        uint32_t v = ld_rlx(ws.sdesc + ((size_t)p * ws.capNTs + k) * C::R + d);
-        uint32_t fl = v & 0xc0000000u;
-        if (fl == 0u) {
-          if (++spins > kSpinLimit || ((spins & 255u) == 0u && ld_rlx(&ws.ctl->error))) {
-            atomicOr(&ws.ctl->error, 1u);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-          continue;
-        }
-        excl += v & kVal32;
-        if (fl == kFlagP32) break;
-        if (--k < t - j) {  // the frame's first tile always holds a prefix
-          atomicOr(&ws.ctl->error, 1u);
-          break;
-        }
-      }
+      excl = look_back32(ws.sdesc + (size_t)p * ws.capNTs * C::R + d, C::R, t - 1, fd.ts0,
+                         ws.ctl);
       st_rlx(mine, kFlagP32 | ((excl + tcnt) & kVal32));
     }
     S.gbase[d] = S.dstart[d] + excl;
@@ -568,14 +747,14 @@ __device__ void sort_tile(const Ws& ws, const Io& io, typename C::Smem& sm, int 
 
   // write runs of equal digits to their global places
   const int dst = (p + 1) & 1;
-  uint32_t* dlo = ws.lo[dst] + f.off;
-  uint32_t* dhi = ws.hi[dst] + f.off;
-  uint32_t* did = ws.idx[dst] + f.off;
+  uint32_t* dlo = ws.lo[dst] + fd.off;
+  uint32_t* dhi = ws.hi[dst] + fd.off;
+  uint32_t* did = ws.idx[dst] + fd.off;
   for (uint32_t i = threadIdx.x; i < tile_total; i += C::BLOCK) {
     const uint32_t lo = S.lo[i], hi = S.hi[i];
     const uint32_t d = digit_of(lo, hi, shift, mask);
     const uint32_t gp = S.gbase[d] + (i - S.tstart[d]);
-    if (gp < (uint32_t)f.n) {
+    if (gp < (uint32_t)fd.n) {
       dlo[gp] = lo;
       if (f.wide) dhi[gp] = hi;
       did[gp] = S.idx[i];
@@ -583,7 +762,7 @@ __device__ void sort_tile(const Ws& ws, const Io& io, typename C::Smem& sm, int 
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    fence_rel();
+    if (persistent) fence_rel();
     atomicAdd(&ws.fs[b].pass_done[p], 1u);
   }
 }
@@ -594,9 +773,40 @@ struct CellOut {
   float r[3];
 };
 
+__device__ __forceinline__ void corner_of(const FrameParams& f, const float p[3], float r[3]) {
+  for (int a = 0; a < 3; ++a)
+    r[a] = __fadd_rn(f.mn[a], __fmul_rn((float)cell_coord(p[a], f.mn[a], f.inv), f.leaf));
+}
+
+// Cell corner from a cell key (the inverse of point_key), so that a segment's
+// corner is known without reading one of its points back.
+__device__ __forceinline__ void corner_of_key(const FrameParams& f, int key_mode, uint32_t lo,
+                                              uint32_t hi, float r[3]) {
+  uint32_t k[3];
+  if (key_mode == 1) {
+    const uint64_t key = ((uint64_t)hi << 32) | lo;
+    k[0] = compact3(key);
+    k[1] = compact3(key >> 1);
+    k[2] = compact3(key >> 2);
+  } else if (!f.wide) {
+    const uint32_t q = lo / f.d[0];
+    k[0] = lo - q * f.d[0];
+    k[2] = q / f.d[1];
+    k[1] = q - k[2] * f.d[1];
+  } else {
+    const uint64_t key = ((uint64_t)hi << 32) | lo;
+    const uint64_t q = key / f.d[0];
+    k[0] = (uint32_t)(key - q * f.d[0]);
+    k[2] = (uint32_t)(q / f.d[1]);
+    k[1] = (uint32_t)(q - (uint64_t)k[2] * f.d[1]);
+  }
+  for (int a = 0; a < 3; ++a) r[a] = __fadd_rn(f.mn[a], __fmul_rn((float)k[a], f.leaf));
+}
+
 // Writes one output row from a segment's sums.
 __device__ __forceinline__ void finalize_row(const Io& io, uint32_t want, int64_t row, int64_t N,
-                                             const Acc& a, uint64_t rgb_wide[3], const CellOut& c) {
+                                             const Acc& a, const uint64_t* rgb_wide,
+                                             const CellOut& c) {
   if (row < 0 || row >= N || a.n == 0 || c.ref >= N) return;
   const float fn = (float)a.n;
   float mean[3];
@@ -614,7 +824,7 @@ __device__ __forceinline__ void finalize_row(const Io& io, uint32_t want, int64_
   }
   if (want & kOutRGB) {
     for (int i = 0; i < 3; ++i) {
-      uint64_t s = rgb_wide ? rgb_wide[i] : (uint64_t)a.rgb[i];
+      const uint64_t s = rgb_wide ? rgb_wide[i] : rgb_channel(a.rgb, i);
       io.crgb[3 * row + i] = (uint8_t)((s + a.n / 2) / a.n);
     }
   }
@@ -623,44 +833,199 @@ __device__ __forceinline__ void finalize_row(const Io& io, uint32_t want, int64_
   if (want & kOutRef) io.ref_index[row] = c.ref;
 }
 
+__device__ __forceinline__ void write_pend(const Ws& ws, int t, int b, int j, const Acc& a,
+                                           const CellOut& c, int64_t row) {
+  Pend pd;
+  pd.valid = 1u;
+  pd.b = (uint32_t)b;
+  pd.j = (uint32_t)j;
+  pd.lo = c.lo;
+  pd.hi = c.hi;
+  for (int q = 0; q < 3; ++q) {
+    pd.r[q] = c.r[q];
+    pd.s[q] = a.s[q];
+    pd.c[q] = a.c[q];
+  }
+  pd.row = row;
+  pd.n = a.n;
+  pd.pad = 0;
+  pd.rgb = a.rgb;
+  ws.pend[t] = pd;
+}
+
+// Fix-up of one reduce tile by one wave: a cell that began in an earlier tile
+// gets the carry-out parts of the tiles it covers, summed in a fixed order.
 template <class C>
-__device__ void red_tile(const Ws& ws, const Io& io, typename C::Smem& sm, int b, int j, int t,
-                         const FrameParams& f, uint32_t want, int B, int NTr, int64_t N) {
-  auto& S = sm.red;
+__device__ void fix_tile(const Ws& ws, const Io& io, int t, int key_mode, uint32_t want,
+                         int64_t N) {
+  const int lane = threadIdx.x & 63;
+  const Pend pd = ws.pend[t];
+  if (!pd.valid) return;
+  const int b = (int)pd.b, j = (int)pd.j;
+  const FrameDesc fd = ws.fd[b];
+  const FrameParams f = frame_params(ws, b, key_mode, C::W);
+  const int fb = f.passes & 1;
+  const uint32_t* klo = ws.lo[fb] + fd.off;
+  const uint32_t* khi = ws.hi[fb] + fd.off;
+  const uint32_t* kid = ws.idx[fb] + fd.off;
+  // where the cell starts: the previous tile knows if the head is there, else
+  // search the frame's sorted keys backwards (galloping, then bisection)
+  uint32_t start = 0, ref = 0;
+  if (lane == 0) {
+    const Frag pf = ws.frag[t - 1];
+    if (pf.head_pos != kNoHead) {
+      start = pf.head_pos;
+      ref = pf.ref;
+    } else {
+      const uint64_t key = ((uint64_t)pd.hi << 32) | pd.lo;
+      uint32_t hi = (uint32_t)((j - 1) * C::TR);  // the cell covers all of tile j-1
+      uint32_t step = (uint32_t)C::TR;
+      uint32_t lo = 0;
+      for (;;) {  // find lo <= start <= hi
+        if (hi <= step) break;
+        const uint32_t probe = hi - step;
+        const uint64_t kp = ((uint64_t)(f.wide ? khi[probe] : 0u) << 32) | klo[probe];
+        if (kp < key) {
+          lo = probe + 1;
+          break;
+        }
+        hi = probe;
+        step *= 2;
+      }
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        const uint64_t km = ((uint64_t)(f.wide ? khi[mid] : 0u) << 32) | klo[mid];
+        if (km < key) lo = mid + 1;
+        else hi = mid;
+      }
+      start = lo;
+      ref = kid[start];
+    }
+  }
+  start = __shfl(start, 0);
+  ref = __shfl(ref, 0);
+  const int th = (int)(start / (uint32_t)C::TR);
+  const int nf = j - th;
+  const int tbase = fd.tr0 + th;
+  Acc part;
+  acc_zero(part);
+  uint64_t rgb3[3] = {0ull, 0ull, 0ull};
+  for (int k = lane; k < nf; k += 64) {
+    const Frag fr = ws.frag[tbase + k];
+    Acc a;
+    a.n = fr.n;
+    for (int q = 0; q < 3; ++q) {
+      a.s[q] = fr.s[q];
+      a.c[q] = fr.c[q];
+    }
+    a.rgb = 0ull;
+    acc_merge(part, a);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) rgb3[q] += rgb_channel(fr.rgb, q);
+  }
+  // butterfly over the wave; partners combine lower lane first, so both hold
+  // the same sums
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    Acc o;
+    o.n = __shfl_xor(part.n, off);
+    for (int q = 0; q < 3; ++q) {
+      o.s[q] = __shfl_xor(part.s[q], off);
+      o.c[q] = __shfl_xor(part.c[q], off);
+    }
+    o.rgb = 0ull;
+    uint64_t orgb[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      orgb[q] = ((uint64_t)__shfl_xor((uint32_t)(rgb3[q] >> 32), off) << 32) |
+                (uint32_t)__shfl_xor((uint32_t)rgb3[q], off);
+    }
+    if (lane & off) {
+      acc_merge(o, part);
+      part = o;
+    } else {
+      acc_merge(part, o);
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) rgb3[q] += orgb[q];
+  }
+  if (lane == 0) {
+    Acc in_tile;
+    in_tile.n = pd.n;
+    for (int q = 0; q < 3; ++q) {
+      in_tile.s[q] = pd.s[q];
+      in_tile.c[q] = pd.c[q];
+    }
+    in_tile.rgb = 0ull;
+    acc_merge(part, in_tile);
+    uint64_t rgbw[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) rgbw[q] = rgb3[q] + rgb_channel(pd.rgb, q);
+    CellOut c;
+    c.lo = pd.lo;
+    c.hi = pd.hi;
+    c.ref = ref;
+    for (int q = 0; q < 3; ++q) c.r[q] = pd.r[q];
+    finalize_row(io, want, pd.row, N, part, rgbw, c);
+  }
+}
+
+template <class C>
+__device__ void red_tile(const Ws& ws, const Io& io, typename C::RedSmem& S, const FrameDesc& fd,
+                         int b, int j, const FrameParams& f, int key_mode, uint32_t want, int B,
+                         int NTr, int64_t N) {
   constexpr int K = C::RI;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int t = fd.tr0 + j;
   const int64_t nv = (f.status == kFrameOk) ? (int64_t)f.n_valid : 0;
   const int64_t s0 = (int64_t)j * C::TR;
   const int64_t e0 = min(s0 + (int64_t)C::TR, nv);
   const int cnt = e0 > s0 ? (int)(e0 - s0) : 0;
   const int fb = f.passes & 1;
-  const uint32_t* klo = ws.lo[fb] + f.off;
-  const uint32_t* khi = ws.hi[fb] + f.off;
-  const uint32_t* kid = ws.idx[fb] + f.off;
+  const uint32_t* klo = ws.lo[fb] + fd.off;
+  const uint32_t* khi = ws.hi[fb] + fd.off;
+  const uint32_t* kid = ws.idx[fb] + fd.off;
   const int base = threadIdx.x * K;
+  const uint32_t Nm1 = (uint32_t)(N - 1);
 
-  // ---- keys and head flags (blocked: thread i owns items i*K .. i*K+K-1)
+  // ---- keys, indices, gathered points (blocked: thread i owns items i*K .. i*K+K-1)
   uint32_t lo_[K], hi_[K], id_[K];
+  float px[K], py[K], pz[K];
+  uint32_t c24[K];
   uint32_t vmask = 0, hmask = 0;
-  {
-    uint32_t plo = 0, phi = 0;
-    bool have_prev = false;
-    if (base < cnt && s0 + base > 0) {
-      plo = klo[s0 + base - 1];
-      phi = f.wide ? khi[s0 + base - 1] : 0u;
-      have_prev = true;
+  uint32_t plo = 0, phi = 0, next_lo = 0, next_hi = 0;
+  bool have_prev = false;
+  if (cnt > 0) {
+    const int64_t lastp = e0 - 1;
+    const int64_t pp = min(max(s0 + base - 1, (int64_t)0), lastp);
+    plo = klo[pp];
+    phi = f.wide ? khi[pp] : 0u;
+    have_prev = base < cnt && s0 + base > 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const int64_t pos = min(s0 + base + i, lastp);
+      lo_[i] = klo[pos];
+      hi_[i] = f.wide ? khi[pos] : 0u;
+      id_[i] = min(kid[pos], Nm1);
     }
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-      lo_[i] = 0u;
-      hi_[i] = 0u;
-      id_[i] = 0u;
+      const float4 r4 = ws.rec[id_[i]];
+      px[i] = r4.x;
+      py[i] = r4.y;
+      pz[i] = r4.z;
+      c24[i] = __float_as_uint(r4.w);
+    }
+    if (threadIdx.x == C::BLOCK - 1 && s0 + C::TR < nv) {
+      next_lo = klo[s0 + C::TR];
+      next_hi = f.wide ? khi[s0 + C::TR] : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
       if (base + i < cnt) {
-        const int64_t pos = s0 + base + i;
-        lo_[i] = klo[pos];
-        hi_[i] = f.wide ? khi[pos] : 0u;
-        id_[i] = kid[pos];
-        if (id_[i] >= (uint64_t)N) id_[i] = 0;  // never for a consistent sort
+        S.klo[base + i] = lo_[i];
+        S.khi[base + i] = hi_[i];
+        S.kid[base + i] = id_[i];
         vmask |= 1u << i;
         const bool head = !have_prev || lo_[i] != plo || hi_[i] != phi;
         if (head) hmask |= 1u << i;
@@ -680,30 +1045,10 @@ __device__ void red_tile(const Ws& ws, const Io& io, typename C::Smem& sm, int b
       st_rlx64(&ws.rdesc[0], kFlagP64 | H);
     } else {
       st_rlx64(&ws.rdesc[t], kFlagA64 | H);
-      int k = t - 1;
-      uint32_t spins = 0;
-      for (;;) {
-        uint64_t v = ld_rlx64(&ws.rdesc[k]);
-        uint64_t fl = v & (3ull << 62);
-        if (fl == 0) {
-          if (++spins > kSpinLimit || ((spins & 255u) == 0u && ld_rlx(&ws.ctl->error))) {
-            atomicOr(&ws.ctl->error, 1u);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-          continue;
-        }
-        excl += v & kVal64;
-        if (fl == kFlagP64) break;
-        if (--k < 0) {
-          atomicOr(&ws.ctl->error, 1u);
-          break;
-        }
-      }
+      excl = look_back64(ws.rdesc, t - 1, ws.ctl);
       st_rlx64(&ws.rdesc[t], kFlagP64 | (excl + H));
     }
     S.excl = excl;
-    S.span_pending = 0;
     if (j == 0) {
       io.out_offsets[b] = (int64_t)excl;
       io.frame_status[b] = ld_rlx(&ws.ctl->error) ? 5 : f.status;
@@ -713,7 +1058,7 @@ __device__ void red_tile(const Ws& ws, const Io& io, typename C::Smem& sm, int b
   __syncthreads();
   const int64_t excl_t = (int64_t)S.excl;
 
-  // ---- gather points, per-item values, thread-sequential segmented sums
+  // ---- per-item values, thread-sequential segmented sums
   Acc pre, cur;
   acc_zero(pre);
   acc_zero(cur);
@@ -723,24 +1068,14 @@ __device__ void red_tile(const Ws& ws, const Io& io, typename C::Smem& sm, int b
   cur_c.lo = cur_c.hi = cur_c.ref = 0;
   pre_c = cur_c;
   for (int i = 0; i < 3; ++i) cur_c.r[i] = pre_c.r[i] = 0.f;
+#pragma unroll
   for (int i = 0; i < K; ++i) {
     if (!((vmask >> i) & 1u)) continue;
-    const uint32_t g = id_[i];
-    const float p[3] = {io.x[g], io.y[g], io.z[g]};
-    uint32_t rgb[3] = {0u, 0u, 0u};
-    if (want & kOutRGB) {
-      rgb[0] = io.rgb[3 * (size_t)g];
-      rgb[1] = io.rgb[3 * (size_t)g + 1];
-      rgb[2] = io.rgb[3 * (size_t)g + 2];
-    }
+    const float p[3] = {px[i], py[i], pz[i]};
     float r[3], dv[3];
-    for (int a = 0; a < 3; ++a) {
-      const uint32_t k = cell_coord(p[a], f.mn[a], f.inv);
-      r[a] = __fadd_rn(f.mn[a], __fmul_rn((float)k, f.leaf));
-      dv[a] = __fsub_rn(p[a], r[a]);
-    }
-    const bool head = (hmask >> i) & 1u;
-    if (head) {
+    corner_of(f, p, r);
+    for (int a = 0; a < 3; ++a) dv[a] = __fsub_rn(p[a], r[a]);
+    if ((hmask >> i) & 1u) {
       if (!seen_head) {
         pre = cur;
         seen_head = true;
@@ -753,15 +1088,15 @@ __device__ void red_tile(const Ws& ws, const Io& io, typename C::Smem& sm, int b
       cur_hp = (uint32_t)(s0 + base + i);
       cur_c.lo = lo_[i];
       cur_c.hi = hi_[i];
-      cur_c.ref = g;
+      cur_c.ref = id_[i];
       for (int a = 0; a < 3; ++a) cur_c.r[a] = r[a];
     } else if (!seen_head && cur.n == 0) {
       pre_c.lo = lo_[i];
       pre_c.hi = hi_[i];
       for (int a = 0; a < 3; ++a) pre_c.r[a] = r[a];
     }
-    acc_add(cur, dv, rgb);
-    if (want & kOutPointCell) io.point_cell[g] = (int32_t)(excl_t + hb + lh - 1);
+    acc_add(cur, dv, c24[i]);
+    if (want & kOutPointCell) io.point_cell[id_[i]] = (int32_t)(excl_t + hb + lh - 1);
   }
   if (!seen_head) pre = cur;
 
@@ -773,7 +1108,7 @@ __device__ void red_tile(const Ws& ws, const Io& io, typename C::Smem& sm, int b
   Seg incl = mine;
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
-    Seg o = seg_shfl_up(incl, off);
+    const Seg o = seg_shfl_up(incl, off);
     if (lane >= off) incl = seg_combine(o, incl);
   }
   if (lane == 63) S.wtot[w] = incl;
@@ -796,248 +1131,272 @@ __device__ void red_tile(const Ws& ws, const Io& io, typename C::Smem& sm, int b
     Acc tot = ex.a;
     acc_merge(tot, pre);
     if (tot.n > 0) {
+      CellOut c = pre_c;  // key/corner from any member
+      if (pre.n == 0) {
+        // all of its members sit before this thread: take the key from LDS
+        const int lp = ex.f ? (int)(ex.hp - (uint32_t)s0) : 0;
+        c.lo = S.klo[lp];
+        c.hi = S.khi[lp];
+        corner_of_key(f, key_mode, c.lo, c.hi, c.r);
+      }
       if (ex.f) {
-        CellOut c = pre.n ? pre_c : cur_c;  // key/corner from any member
-        if (pre.n == 0) {
-          // all of its members sit in earlier threads: read them back
-          const uint32_t pos = ex.hp;
-          c.lo = klo[pos];
-          c.hi = f.wide ? khi[pos] : 0u;
-          const uint32_t g = min(kid[pos], (uint32_t)(N - 1));
-          const float p[3] = {io.x[g], io.y[g], io.z[g]};
-          for (int a = 0; a < 3; ++a)
-            c.r[a] = __fadd_rn(f.mn[a], __fmul_rn((float)cell_coord(p[a], f.mn[a], f.inv), f.leaf));
-        }
-        c.ref = kid[ex.hp];
+        c.ref = S.kid[ex.hp - (uint32_t)s0];
         finalize_row(io, want, excl_t + hb - 1, N, tot, nullptr, c);
       } else {
-        // opened in an earlier tile: combined below with the earlier tiles' parts
-        CellOut c = pre.n ? pre_c : cur_c;
-        if (pre.n == 0) {
-          const int64_t pos = s0;  // the tile's first item belongs to it
-          c.lo = klo[pos];
-          c.hi = f.wide ? khi[pos] : 0u;
-          const uint32_t g = min(kid[pos], (uint32_t)(N - 1));
-          const float p[3] = {io.x[g], io.y[g], io.z[g]};
-          for (int a = 0; a < 3; ++a)
-            c.r[a] = __fadd_rn(f.mn[a], __fmul_rn((float)cell_coord(p[a], f.mn[a], f.inv), f.leaf));
-        }
-        S.span_acc = tot;
-        S.span_lo = c.lo;
-        S.span_hi = c.hi;
-        for (int a = 0; a < 3; ++a) S.span_r[a] = c.r[a];
-        S.span_pending = 1;
+        // opened in an earlier tile: the fix-up phase adds the earlier parts
+        write_pend(ws, t, b, j, tot, c, excl_t - 1);
       }
     }
   }
   // (ii) the thread holding the tile's last item closes or hands on the last segment
   if (cnt > 0 && base < cnt && base + K >= cnt) {
-    Seg last = seg_combine(ex, mine);
+    const Seg last = seg_combine(ex, mine);
+    const int li = cnt - 1 - base;
     const int64_t e = s0 + cnt;
     bool cont = false;
-    if (e < nv) {
-      cont = klo[e] == lo_[cnt - 1 - base] && (!f.wide || khi[e] == hi_[cnt - 1 - base]);
+    uint32_t llo = 0, lhi = 0, lid = 0;
+    float lp[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      if (i == li) {
+        llo = lo_[i];
+        lhi = hi_[i];
+        lid = id_[i];
+        lp[0] = px[i];
+        lp[1] = py[i];
+        lp[2] = pz[i];
+      }
     }
+    if (e < nv) cont = next_lo == llo && (!f.wide || next_hi == lhi);
     CellOut c;
-    c.lo = lo_[cnt - 1 - base];
-    c.hi = hi_[cnt - 1 - base];
-    {
-      const uint32_t g = id_[cnt - 1 - base];
-      const float p[3] = {io.x[g], io.y[g], io.z[g]};
-      for (int a = 0; a < 3; ++a)
-        c.r[a] = __fadd_rn(f.mn[a], __fmul_rn((float)cell_coord(p[a], f.mn[a], f.inv), f.leaf));
-    }
+    c.lo = llo;
+    c.hi = lhi;
+    c.ref = lid;
+    corner_of(f, lp, c.r);
     if (cont) {
       Frag fr;
       fr.n = last.a.n;
       for (int a = 0; a < 3; ++a) {
         fr.s[a] = last.a.s[a];
         fr.c[a] = last.a.c[a];
-        fr.rgb[a] = last.a.rgb[a];
       }
-      fr.pad[0] = fr.pad[1] = 0;
+      fr.head_pos = last.f ? last.hp : kNoHead;
+      fr.ref = last.f ? S.kid[last.hp - (uint32_t)s0] : 0u;
+      fr.pad = 0;
+      fr.rgb = last.a.rgb;
       ws.frag[t] = fr;
       fence_rel();
       st_rlx(&ws.fflag[t], 1u);
     } else if (last.f) {
-      c.ref = kid[last.hp];
+      c.ref = S.kid[last.hp - (uint32_t)s0];
       finalize_row(io, want, excl_t + (int64_t)H - 1, N, last.a, nullptr, c);
     } else {
-      S.span_acc = last.a;
-      S.span_lo = c.lo;
-      S.span_hi = c.hi;
-      for (int a = 0; a < 3; ++a) S.span_r[a] = c.r[a];
-      S.span_pending = 1;
+      write_pend(ws, t, b, j, last.a, c, excl_t - 1);
     }
   }
-  __syncthreads();
 
-  // ---- a segment that began in an earlier tile and ends in this one
-  if (S.span_pending) {
-    if (threadIdx.x == 0) {
-      // first position of this key in the frame's sorted keys
-      uint32_t lo = 0, hi = (uint32_t)s0;
-      const uint64_t key = ((uint64_t)S.span_hi << 32) | S.span_lo;
-      while (lo < hi) {
-        uint32_t mid = (lo + hi) >> 1;
-        uint64_t km = ((uint64_t)(f.wide ? khi[mid] : 0u) << 32) | klo[mid];
-        if (km < key) lo = mid + 1;
-        else hi = mid;
-      }
-      S.span_start = lo;
-    }
-    __syncthreads();
-    const uint32_t start = S.span_start;
-    const int th = (int)(start / (uint32_t)C::TR);
-    const int nf = j - th;
-    const int tbase = (int)ws.tpr[b] + th;
-    Acc part;
-    acc_zero(part);
-    uint64_t wide_rgb[3] = {0, 0, 0};
-    for (int k = threadIdx.x; k < nf; k += C::BLOCK) {
-      if (wait_geq(&ws.fflag[tbase + k], 1u, ws.ctl)) fence_acq();
-      const Frag fr = ws.frag[tbase + k];
-      Acc a;
-      a.n = fr.n;
-      for (int q = 0; q < 3; ++q) {
-        a.s[q] = fr.s[q];
-        a.c[q] = fr.c[q];
-        a.rgb[q] = 0u;
-        wide_rgb[q] += fr.rgb[q];
-      }
-      acc_merge(part, a);
-    }
-    S.part[threadIdx.x] = part;
-    __syncthreads();
-    for (int stride = C::BLOCK / 2; stride > 0; stride >>= 1) {
-      if ((int)threadIdx.x < stride) {
-        Acc a = S.part[threadIdx.x];
-        acc_merge(a, S.part[threadIdx.x + stride]);
-        S.part[threadIdx.x] = a;
-      }
-      __syncthreads();
-    }
-    // colour sums of the parts, 64-bit: reuse the part slots thread by thread
-    for (int q = 0; q < 3; ++q) {
-      S.part[threadIdx.x].rgb[0] = (uint32_t)wide_rgb[q];
-      S.part[threadIdx.x].rgb[1] = (uint32_t)(wide_rgb[q] >> 32);
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        uint64_t sum = 0;
-        for (int i = 0; i < C::BLOCK; ++i)
-          sum += ((uint64_t)S.part[i].rgb[1] << 32) | S.part[i].rgb[0];
-        wide_rgb[q] = sum;
-      }
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      Acc tot = S.part[0];
-      acc_merge(tot, S.span_acc);
-      uint64_t rgbw[3];
-      for (int q = 0; q < 3; ++q) rgbw[q] = wide_rgb[q] + S.span_acc.rgb[q];
-      CellOut c;
-      c.lo = S.span_lo;
-      c.hi = S.span_hi;
-      c.ref = kid[start];
-      for (int a = 0; a < 3; ++a) c.r[a] = S.span_r[a];
-      finalize_row(io, want, excl_t - 1, N, tot, rgbw, c);
-    }
-  }
 }
 
 // ---------------------------------------------------------- pipeline ----
+// Thread 0 of a workgroup: take the next item, find its frame, wait for its
+// inputs (once per frame and phase), prepare the frame's grid parameters.
 template <class C>
-__device__ __forceinline__ int find_frame(const uint32_t* tp, int B, int t) {
-  int lo = 0, hi = B;  // largest b with tp[b] <= t
-  while (hi - lo > 1) {
-    int mid = (lo + hi) >> 1;
-    if ((int)tp[mid] <= t) lo = mid;
-    else hi = mid;
-  }
-  return lo;
-}
-
-template <class C>
-__global__ __launch_bounds__(C::BLOCK) void vg_pipeline_kernel(Ws ws, int ph_lo, int ph_hi) {
-  __shared__ typename C::Smem sm;
-  __shared__ uint32_t s_item;
-  const CallHdr hdr = *ws.hdr;
-  const Io io = *ws.io;
-  const int B = hdr.B, NTs = hdr.NTs, NTr = hdr.NTr;
-  const bool persistent = (ph_lo == 0 && ph_hi == C::NPH);
-  uint32_t* counter = persistent ? &ws.ctl->queue[0] : &ws.ctl->queue[1 + ph_lo];
-  const uint32_t total = persistent ? (uint32_t)(C::PH_RED * NTs + NTr)
-                                    : (uint32_t)(ph_lo == C::PH_RED ? NTr : NTs);
+__device__ __forceinline__ void next_item(const Ws& ws, const CallHdr& hdr, BlockCtl& bc,
+                                       uint32_t* counter, bool persistent, int ph_lo,
+                                       uint32_t total) {
   for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
-    __syncthreads();
-    const uint32_t item = s_item;
-    __syncthreads();
-    if (item >= total) break;
+    const uint32_t item = atomicAdd(counter, 1u);
+    bc.item = item;
+    bc.skip = 0;
+    if (item >= total) return;
     int ph, t;
-    uint32_t phase_base;
+    uint32_t base;
+    const uint32_t nb = (uint32_t)hdr.NTb, ns = (uint32_t)hdr.NTs;
     if (persistent) {
-      ph = min((int)(item / (uint32_t)NTs), C::PH_RED);
-      phase_base = (uint32_t)ph * (uint32_t)NTs;
-      t = (int)(item - phase_base);
+      if (item < nb) { ph = C::PH_BBOX; base = 0; }
+      else if (item < 2 * nb) { ph = C::PH_HIST; base = nb; }
+      else if (item < 2 * nb + C::MAXP * ns) {
+        ph = C::PH_SORT0 + (int)((item - 2 * nb) / ns);
+        base = 2 * nb + (uint32_t)(ph - C::PH_SORT0) * ns;
+      } else if (item < 2 * nb + C::MAXP * ns + (uint32_t)hdr.NTr) {
+        ph = C::PH_RED;
+        base = 2 * nb + C::MAXP * ns;
+      } else {
+        ph = C::PH_FIX;
+        base = 2 * nb + C::MAXP * ns + (uint32_t)hdr.NTr;
+      }
     } else {
       ph = ph_lo;
-      phase_base = 0;
-      t = (int)item;
+      base = 0;
     }
-    const bool red = ph == C::PH_RED;
-    const uint32_t* tp = red ? ws.tpr : ws.tps;
-    const int b = find_frame<C>(tp, B, t);
-    const int j = t - (int)tp[b];
-    const int ntb = (int)(ws.tps[b + 1] - ws.tps[b]);
-    if (ph == C::PH_BBOX) {
-      bbox_tile<C>(ws, io, sm, b, j, hdr.want);
+    t = (int)(item - base);
+    if (ph == C::PH_FIX) {
+      // fix-ups read the carry-out parts and pending cells of every reduce tile
+      bc.ph = ph;
+      bc.t = t;
+      bc.b = 0;
+      bc.j = 0;
+      if (persistent && bc.dep_b[ph] != 0) {
+        wait_geq(&ws.ctl->red_tiles_done, (uint32_t)hdr.NTr, ws.ctl);
+        fence_acq();
+        bc.dep_b[ph] = 0;
+      }
+      return;
+    }
+    const uint32_t tiling = ph <= C::PH_HIST ? 0u : (ph == C::PH_RED ? 2u : 1u);
+    int b, j;
+    if (hdr.B <= kLdsFrames) {
+      const uint32_t* tp = bc.tp[tiling];
+      int lo = 0, hi = hdr.B;  // largest b with tp[b] <= t
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((int)tp[mid] <= t) lo = mid;
+        else hi = mid;
+      }
+      b = lo;
+      j = t - (int)tp[lo];
     } else {
-      // wait for what this tile depends on
-      if (threadIdx.x == 0) {
-        wait_geq(&ws.fs[b].bbox_done, (uint32_t)ntb, ws.ctl);
-        if (ph >= C::PH_SORT0) wait_geq(&ws.fs[b].hist_done, (uint32_t)ntb, ws.ctl);
+      const uint32_t toff = tiling == 0 ? 0u : (tiling == 1 ? nb : nb + ns);
+      const uint2 ti = ws.tinfo[toff + t];
+      b = (int)ti.x;
+      j = (int)ti.y;
+    }
+    if (bc.fd_b != b) {
+      bc.fd = ws.fd[b];
+      bc.fd_b = b;
+    }
+    bc.ph = ph;
+    bc.t = t;
+    bc.b = b;
+    bc.j = j;
+    if (ph == C::PH_BBOX) return;
+    const FrameDesc& fd = bc.fd;
+    // grid parameters need the frame's bounding box
+    if (bc.fp_b != b) {
+      if (persistent) {
+        wait_geq(&ws.fs[b].bbox_done, (uint32_t)fd.ntb, ws.ctl);
         fence_acq();
       }
-      __syncthreads();
-      fence_acq();
-      const FrameParams f = frame_params(ws, b, hdr.key_mode, C::W);
-      if (ph == C::PH_HIST) {
-        hist_tile<C>(ws, io, sm, b, j, t, f, hdr.key_mode, hdr.want);
-      } else if (ph < C::PH_RED) {
-        const int p = ph - C::PH_SORT0;
-        if (p >= f.passes) {
-          // nothing of this frame in this pass: let the queue jump past it
-          if (threadIdx.x == 0)
-            atomicMax(counter, phase_base + ws.tps[b + 1]);
-        } else {
-          if (p > 0) {
-            if (threadIdx.x == 0) {
-              wait_geq(&ws.fs[b].pass_done[p - 1], (uint32_t)ntb, ws.ctl);
-              fence_acq();
-            }
-            __syncthreads();
-            fence_acq();
-          }
-          sort_tile<C>(ws, io, sm, b, j, t, p, f, hdr.key_mode);
-        }
-      } else {
-        if (f.passes > 0 && f.status == kFrameOk) {
-          if (threadIdx.x == 0) {
-            wait_geq(&ws.fs[b].pass_done[f.passes - 1], (uint32_t)ntb, ws.ctl);
-            fence_acq();
-          }
-          __syncthreads();
+      bc.fp = frame_params(ws, b, hdr.key_mode, C::W);
+      bc.fp_b = b;
+    }
+    const FrameParams& f = bc.fp;
+    if (ph == C::PH_HIST) return;
+    if (ph < C::PH_RED) {
+      const int p = ph - C::PH_SORT0;
+      if (p >= f.passes) {
+        // no work for this frame in this pass: jump the queue past it, or past
+        // every remaining pass once no frame needs this one
+        uint32_t jump = base + (uint32_t)(fd.ts0 + fd.nts);
+        const bool all_hist = wait_geq(&ws.ctl->hist_tiles_done, (uint32_t)hdr.NTb, ws.ctl);
+        if (persistent) fence_acq();
+        if (all_hist && (uint32_t)p >= ld_rlx(&ws.ctl->max_passes))
+          jump = persistent ? 2 * nb + C::MAXP * ns : total;
+        atomicMax(counter, jump);
+        continue;
+      }
+      if (bc.dep_b[ph] != b) {
+        if (persistent) {
+          wait_geq(&ws.fs[b].hist_done, (uint32_t)fd.ntb, ws.ctl);
+          if (p > 0) wait_geq(&ws.fs[b].pass_done[p - 1], (uint32_t)fd.nts, ws.ctl);
           fence_acq();
         }
-        red_tile<C>(ws, io, sm, b, j, t, f, hdr.want, B, NTr, hdr.N);
+        bc.dep_b[ph] = b;
+      }
+      return;
+    }
+    // reduce: the frame's last radix pass must be complete
+    if (bc.dep_b[ph] != b) {
+      if (persistent && f.passes > 0 && f.status == kFrameOk) {
+        wait_geq(&ws.fs[b].hist_done, (uint32_t)fd.ntb, ws.ctl);
+        wait_geq(&ws.fs[b].pass_done[f.passes - 1], (uint32_t)fd.nts, ws.ctl);
+        fence_acq();
+      }
+      bc.dep_b[ph] = b;
+    }
+    return;
+  }
+}
+
+// Kernel entry points.  KIND selects which phases a kernel holds: all of them
+// (one persistent launch over the whole queue) or one phase kind (one launch
+// per phase).  Every kind runs the same tile code; a kernel that holds one
+// kind only is compiled with that kind's register and LDS needs.
+enum Kind : int { kAll = 0, kBbox = 1, kHist = 2, kSort = 3, kRed = 4, kFix = 5 };
+
+template <class C, int KIND>
+__global__ __launch_bounds__(C::BLOCK) void vg_pipeline_kernel(Ws ws, int ph_lo, int ph_hi) {
+  __shared__ typename SmemOf<C, KIND>::type sm;
+  __shared__ BlockCtl bc;
+  const CallHdr hdr = *ws.hdr;
+  const Io io = *ws.io;
+  const bool persistent = (ph_lo == 0 && ph_hi == C::NPH);
+  uint32_t* counter = persistent ? &ws.ctl->queue[0] : &ws.ctl->queue[1 + ph_lo];
+  uint32_t total;
+  const uint32_t nfix = (uint32_t)((hdr.NTr + C::NW - 1) / C::NW);
+  if (persistent) total = (uint32_t)(2 * hdr.NTb + C::MAXP * hdr.NTs + hdr.NTr) + nfix;
+  else if (ph_lo <= C::PH_HIST) total = (uint32_t)hdr.NTb;
+  else if (ph_lo == C::PH_RED) total = (uint32_t)hdr.NTr;
+  else if (ph_lo == C::PH_FIX) total = nfix;
+  else total = (uint32_t)hdr.NTs;
+  if (hdr.B <= kLdsFrames) {
+    for (int i = threadIdx.x; i <= hdr.B; i += C::BLOCK) {
+      bc.tp[0][i] = ws.tpb[i];
+      bc.tp[1][i] = ws.tps[i];
+      bc.tp[2][i] = ws.tpr[i];
+    }
+  }
+  if (threadIdx.x == 0) {
+    bc.fp_b = -1;
+    bc.fd_b = -1;
+    for (int i = 0; i < kMaxPassSlots + 3; ++i) bc.dep_b[i] = -1;
+    // a one-pass launch of a radix pass no frame needs ends at once
+    bc.item = 0;
+    if (!persistent && ph_lo >= C::PH_SORT0 && ph_lo < C::PH_RED &&
+        (uint32_t)(ph_lo - C::PH_SORT0) >= ld_rlx(&ws.ctl->max_passes))
+      bc.item = total;
+  }
+  __syncthreads();
+  if (bc.item >= total && total > 0) return;
+  for (;;) {
+    if (threadIdx.x == 0) next_item<C>(ws, hdr, bc, counter, persistent, ph_lo, total);
+    __syncthreads();
+    if (bc.item >= total) break;
+    const int ph = bc.ph, b = bc.b, j = bc.j;
+    const FrameDesc fd = bc.fd;
+    if (ph == C::PH_BBOX) {
+      if constexpr (KIND == kAll || KIND == kBbox)
+        bbox_tile<C>(ws, io, sm.bbox, fd, b, j, hdr.want, persistent);
+    } else if (ph == C::PH_FIX) {
+      if constexpr (KIND == kAll || KIND == kFix) {
+        const int t = bc.t * C::NW + (int)(threadIdx.x >> 6);
+        if (t < hdr.NTr) fix_tile<C>(ws, io, t, hdr.key_mode, hdr.want, hdr.N);
+      }
+    } else {
+      const FrameParams f = bc.fp;
+      if (ph == C::PH_HIST) {
+        if constexpr (KIND == kAll || KIND == kHist)
+          hist_tile<C>(ws, io, sm.hist, fd, b, j, f, hdr.key_mode, hdr.want, persistent);
+      } else if (ph < C::PH_RED) {
+        if constexpr (KIND == kAll || KIND == kSort)
+          sort_tile<C>(ws, io, sm.sort, fd, b, j, ph - C::PH_SORT0, f, hdr.key_mode, persistent);
+      } else {
+        if constexpr (KIND == kAll || KIND == kRed) {
+          red_tile<C>(ws, io, sm.red, fd, b, j, f, hdr.key_mode, hdr.want, hdr.B, hdr.NTr, hdr.N);
+          __syncthreads();
+          if (threadIdx.x == 0) {
+            if (persistent) fence_rel();
+            atomicAdd(&ws.ctl->red_tiles_done, 1u);
+          }
+        }
       }
     }
     __syncthreads();
   }
 }
 
-// Clears the per-call state (a fill kernel: graph-safe, no memset nodes).
+// Clears the per-call state and builds the tile -> (frame, tile) tables
+// (a fill kernel: graph-safe, no memset nodes).
 __global__ void vg_init_kernel(Ws ws) {
   const CallHdr hdr = *ws.hdr;
   const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1050,6 +1409,22 @@ __global__ void vg_init_kernel(Ws ws) {
   for (size_t i = tid; i < (size_t)hdr.NTr; i += nth) {
     ws.rdesc[i] = 0ull;
     ws.fflag[i] = 0u;
+    ws.pend[i].valid = 0u;
+  }
+  const size_t ntot = (size_t)hdr.NTb + hdr.NTs + hdr.NTr;
+  for (size_t i = tid; i < ntot; i += nth) {
+    const uint32_t* tp;
+    uint32_t t;
+    if (i < (size_t)hdr.NTb) { tp = ws.tpb; t = (uint32_t)i; }
+    else if (i < (size_t)hdr.NTb + hdr.NTs) { tp = ws.tps; t = (uint32_t)(i - hdr.NTb); }
+    else { tp = ws.tpr; t = (uint32_t)(i - hdr.NTb - hdr.NTs); }
+    int lo = 0, hi = hdr.B;  // largest b with tp[b] <= t
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (tp[mid] <= t) lo = mid;
+      else hi = mid;
+    }
+    ws.tinfo[i] = make_uint2((uint32_t)lo, t - tp[lo]);
   }
 }
 
