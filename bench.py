@@ -48,13 +48,13 @@ def frame_passes(x, y, z, leaf, radix_bits):
     return max(1, math.ceil(bits / radix_bits))
 
 
-def algorithmic_bytes(n, nv, passes, m):
+def algorithmic_bytes(n, nv, passes, m, point_cell=False):
     """Bytes the sort-based method moves per call: bbox and key read xyz of every
     point (12 + 12 B), the key pass writes (key, index) of valid points (8 B),
     the histogram reads keys (4 B), each radix pass reads and writes pairs
-    (16 B), the reduce reads pairs (8 B) and gathers xyz + rgb (15 B) and writes
-    the per-point row (4 B), and every cell writes xyz, rgb, count, key (27 B)."""
-    return 24 * n + (8 + 4 + 16 * passes + 8 + 15 + 4) * nv + 27 * m
+    (16 B), the reduce reads pairs (8 B) and gathers xyz + rgb (15 B), and every
+    cell writes xyz, rgb, count, key (27 B); the per-point row adds 4 B."""
+    return 24 * n + (8 + 4 + 16 * passes + 8 + 15 + (4 if point_cell else 0)) * nv + 27 * m
 
 
 def main():
@@ -64,10 +64,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--frames", type=int, default=64)
     ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--exec-mode", choices=["persistent", "phased"], default="persistent")
+    ap.add_argument("--exec-mode", choices=["persistent", "phased", "tuned"], default="tuned",
+                    help="launch form; tuned = the one in the tuning file (else the built-in default)")
     ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2102_11084_amd", "tuning_gfx950.json"))
     ap.add_argument("--set", action="append", default=[], metavar="FIELD=VALUE",
                     help="override a tuning field, e.g. --set sort_items=8")
+    ap.add_argument("--point-cell", action="store_true",
+                    help="also write every input point's output row (needed for the backward)")
     ap.add_argument("--no-legs", action="store_true", help="skip plain/backward legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -85,8 +88,8 @@ def main():
 
     dev = torch.device("cuda:0")
     tuning = vg.load_tuning(args.tuning) if os.path.exists(args.tuning) else vg.default_tuning()
-    if args.exec_mode == "phased":
-        tuning.exec_mode = vg.EXEC_PHASED
+    if args.exec_mode != "tuned":
+        tuning.exec_mode = vg.EXEC_PHASED if args.exec_mode == "phased" else vg.EXEC_PERSISTENT
     for kv in args.set:
         k, v = kv.split("=", 1)
         setattr(tuning, k, int(v))
@@ -101,7 +104,8 @@ def main():
     log(f"generated {len(leaves)} frames, {N} points ({nv_frames.sum()} valid) in {time.time() - t0:.1f}s")
     d = [torch.from_numpy(a).to(dev) for a in (x, y, z, rgb.reshape(-1))]
     plan = vg.BatchPlan(len(leaves), N, vg.KEY_LINEAR, tuning, use_graph=not args.no_graph)
-    outs = plan.alloc_outputs(N, len(leaves), dev, outputs=("xyz", "rgb", "count", "key", "point_cell"))
+    out_set = ("xyz", "rgb", "count", "key") + (("point_cell",) if args.point_cell else ())
+    outs = plan.alloc_outputs(N, len(leaves), dev, outputs=out_set)
     stream = torch.cuda.current_stream(dev)
 
     for _ in range(args.warmup):
@@ -131,7 +135,7 @@ def main():
     passes = np.array([frame_passes(x[offs[b]:offs[b + 1]], y[offs[b]:offs[b + 1]],
                                     z[offs[b]:offs[b + 1]], leaves[b], radix) for b in range(len(leaves))])
     alg = sum(algorithmic_bytes(int(offs[b + 1] - offs[b]), int(nv_frames[b]), int(passes[b]),
-                                int(m_frames[b])) for b in range(len(leaves)))
+                                int(m_frames[b]), args.point_cell) for b in range(len(leaves)))
     achieved = alg / (ev_ms * 1e-3) / 1e9
     floor_bytes = 15 * int(nv_frames.sum()) + 27 * int(m_frames.sum())
     result = {
@@ -145,7 +149,7 @@ def main():
                         "from a hipGraph",
             "frames": int(len(leaves)), "points": N, "valid_points": int(nv_frames.sum()),
             "cells": int(m_frames.sum()), "radix_passes": [int(p) for p in passes],
-            "tuning": tuning.as_dict(), "graph": not args.no_graph,
+            "tuning": tuning.as_dict(), "graph": not args.no_graph, "outputs": list(out_set),
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -168,7 +172,7 @@ def main():
             p0 = time.perf_counter()
             for b in range(len(leaves)):
                 vg.voxel_downsample(*frames_dev[b], leaf=float(leaves[b]), tuning=tuning,
-                                    outputs=("xyz", "rgb", "count", "key", "point_cell"), workspace=ws)
+                                    outputs=out_set, workspace=ws)
             torch.cuda.synchronize()
             plain_s = time.perf_counter() - p0
         plain = N / plain_s / 1e6

@@ -71,7 +71,7 @@ const Variant kVariants[] = {
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
-const vg_tuning kDefaultTuning = {256, 16, 8, 256, 8, 0, VG_EXEC_PERSISTENT};
+const vg_tuning kDefaultTuning = {512, 8, 8, 512, 4, 0, VG_EXEC_PHASED};
 
 const Variant* find_variant(const vg_tuning* t) {
   if (!t) t = &kDefaultTuning;
@@ -110,7 +110,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
   int64_t capN;
   int capB, capNTb, capNTs, capNTr, slots, R;
-  size_t hdr, io, fd, tpb, tps, tpr, staged;   // staged = bytes copied from the host each call
+  size_t hdr, io, fd, tpb, tps, tpr, ilv_s, ilv_perm, staged;  // staged: copied from the host
   size_t tinfo, ctl, fs, hist, sdesc, rdesc, fflag, frag, pend, lo0, lo1, hi0, hi1, id0, id1, rec,
       outoff, fstat;
   size_t total;
@@ -134,6 +134,8 @@ Layout make_layout(int64_t capN, int capB, const Variant& v) {
   L.tpb = o;  o = align_up(o + 4 * (size_t)(L.capB + 1));
   L.tps = o;  o = align_up(o + 4 * (size_t)(L.capB + 1));
   L.tpr = o;  o = align_up(o + 4 * (size_t)(L.capB + 1));
+  L.ilv_s = o; o = align_up(o + 4 * (size_t)(kIlvMaxRounds + 1));
+  L.ilv_perm = o; o = align_up(o + 4 * (size_t)kIlvMaxFrames);
   L.staged = o;
   L.tinfo = o; o = align_up(o + 8 * ((size_t)L.capNTb + L.capNTs + L.capNTr));
   L.ctl = o;  o = align_up(o + sizeof(Ctl));
@@ -168,6 +170,8 @@ Ws carve(const Layout& L, void* base) {
   w.tps = reinterpret_cast<uint32_t*>(b + L.tps);
   w.tinfo = reinterpret_cast<uint2*>(b + L.tinfo);
   w.tpr = reinterpret_cast<uint32_t*>(b + L.tpr);
+  w.ilv_s = reinterpret_cast<uint32_t*>(b + L.ilv_s);
+  w.ilv_perm = reinterpret_cast<uint32_t*>(b + L.ilv_perm);
   w.ctl = reinterpret_cast<Ctl*>(b + L.ctl);
   w.fs = reinterpret_cast<FrameState*>(b + L.fs);
   w.hist = reinterpret_cast<uint32_t*>(b + L.hist);
@@ -286,6 +290,25 @@ bool fill_staging(char* st, const Layout& L, const Variant& v, const vg_points* 
   tps[B] = (uint32_t)ts;
   tpr[B] = (uint32_t)tr;
   if (tb > L.capNTb || ts > L.capNTs || tr > L.capNTr) return false;
+  // round-robin order of the sort tiles over frames (when the tables fit)
+  hdr.ilv_rounds = 0;
+  if (B > 1 && B <= kIlvMaxFrames) {
+    int32_t maxnt = 0;
+    for (int b = 0; b < B; ++b) maxnt = std::max(maxnt, fd[b].nts);
+    if (maxnt <= kIlvMaxRounds) {
+      uint32_t* perm = reinterpret_cast<uint32_t*>(st + L.ilv_perm);
+      uint32_t* S = reinterpret_cast<uint32_t*>(st + L.ilv_s);
+      for (int b = 0; b < B; ++b) perm[b] = (uint32_t)b;
+      std::stable_sort(perm, perm + B, [&](uint32_t a, uint32_t c) { return fd[a].nts > fd[c].nts; });
+      int cnt = B;  // frames with more than r tiles
+      S[0] = 0;
+      for (int r = 0; r < maxnt; ++r) {
+        while (cnt > 0 && fd[perm[cnt - 1]].nts <= r) --cnt;
+        S[r + 1] = S[r] + (uint32_t)cnt;
+      }
+      hdr.ilv_rounds = maxnt;
+    }
+  }
   hdr.NTb = (int32_t)tb;
   hdr.NTs = (int32_t)ts;
   hdr.NTr = (int32_t)tr;

@@ -34,7 +34,16 @@ struct CallHdr {
   int32_t NTb, NTs, NTr;
   uint32_t want;        // output mask (kOut*)
   int64_t N;            // points over all frames
+  int32_t ilv_rounds;   // > 0: radix-pass tiles are taken round-robin over frames
+  int32_t pad;
 };
+
+// Round-robin order of the radix-pass tiles: round j holds tile j of every
+// frame with more than j sort tiles, frames by descending tile count.  Each
+// frame's tiles stay in order, and tiles of one frame are spread in time, so
+// the per-frame look-back chains stay short.
+constexpr int kIlvMaxRounds = 1024;
+constexpr int kIlvMaxFrames = 256;
 
 enum : uint32_t {
   kOutXYZ = 1, kOutRGB = 2, kOutCount = 4, kOutKey = 8, kOutPointCell = 16, kOutRef = 32,
@@ -110,6 +119,8 @@ struct Ws {
   uint32_t* tpb;        // [B+1] big-tile prefix over frames
   uint32_t* tps;        // [B+1] sort-tile prefix over frames
   uint32_t* tpr;        // [B+1] reduce-tile prefix over frames
+  uint32_t* ilv_s;      // [rounds+1] first item of each round
+  uint32_t* ilv_perm;   // [B] frames by descending sort-tile count
   uint2* tinfo;         // [NTb + NTs + NTr]: (frame, tile within frame)
   Ctl* ctl;
   FrameState* fs;       // [B]

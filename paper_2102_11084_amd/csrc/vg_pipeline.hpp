@@ -100,22 +100,23 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* wsum, 
 
 // Decoupled look-back: sum the published values of tiles k0, k0-1, ... down
 // to the first inclusive prefix.  LB descriptors are read per round trip.
-constexpr int kLookBatch = 4;
+constexpr int kLookBatchSort = 4;   // per digit, per round trip
+constexpr int kLookBatchRow = 16;   // row-count chain, per round trip
 
 __device__ __forceinline__ uint32_t look_back32(const uint32_t* desc, size_t stride, int k0,
                                                 int lo, Ctl* ctl) {
+  constexpr int LB = kLookBatchSort;
   uint32_t excl = 0;
   int k = k0;
   uint32_t spins = 0;
   for (;;) {
-    uint32_t v[kLookBatch];
+    uint32_t v[LB];
 #pragma unroll
-    for (int i = 0; i < kLookBatch; ++i)
+    for (int i = 0; i < LB; ++i)
       v[i] = (k - i >= lo) ? ld_rlx(desc + (size_t)(k - i) * stride) : kFlagP32;
     int used = 0;
     bool done = false;
-#pragma unroll
-    for (int i = 0; i < kLookBatch; ++i) {
+    for (int i = 0; i < LB; ++i) {
       if (done || used < i) break;
       const uint32_t fl = v[i] & 0xc0000000u;
       if (fl == 0u) break;
@@ -140,17 +141,17 @@ __device__ __forceinline__ uint32_t look_back32(const uint32_t* desc, size_t str
 }
 
 __device__ __forceinline__ uint64_t look_back64(const uint64_t* desc, int k0, Ctl* ctl) {
+  constexpr int LB = kLookBatchRow;
   uint64_t excl = 0;
   int k = k0;
   uint32_t spins = 0;
   for (;;) {
-    uint64_t v[kLookBatch];
+    uint64_t v[LB];
 #pragma unroll
-    for (int i = 0; i < kLookBatch; ++i) v[i] = (k - i >= 0) ? ld_rlx64(desc + (k - i)) : kFlagP64;
+    for (int i = 0; i < LB; ++i) v[i] = (k - i >= 0) ? ld_rlx64(desc + (k - i)) : kFlagP64;
     int used = 0;
     bool done = false;
-#pragma unroll
-    for (int i = 0; i < kLookBatch; ++i) {
+    for (int i = 0; i < LB; ++i) {
       if (done || used < i) break;
       const uint64_t fl = v[i] & (3ull << 62);
       if (fl == 0) break;
@@ -312,10 +313,10 @@ __device__ __forceinline__ void acc_merge(Acc& a, const Acc& b) {
   a.rgb += b.rgb;
 }
 
-// Segmented-scan element: f = a head lies in the covered range, hp = frame
-// position of the last such head, a = sums since that head (or since the start).
+// Segmented-scan element: f = a head lies in the covered range, a = sums since
+// the last such head (or since the start).
 struct Seg {
-  uint32_t f, hp;
+  uint32_t f;
   Acc a;
 };
 
@@ -329,7 +330,6 @@ __device__ __forceinline__ Seg seg_combine(const Seg& x, const Seg& y) {
 __device__ __forceinline__ Seg seg_shfl_up(const Seg& v, int off) {
   Seg r;
   r.f = __shfl_up(v.f, off);
-  r.hp = __shfl_up(v.hp, off);
   r.a.n = __shfl_up(v.a.n, off);
   for (int i = 0; i < 3; ++i) {
     r.a.s[i] = __shfl_up(v.a.s[i], off);
@@ -347,7 +347,7 @@ struct Cfg {
   static constexpr int NW = BLOCK / 64;
   static constexpr int SI = SORT_ITEMS_;
   static constexpr int TS = BLOCK * SI;      // sort tile
-  static constexpr int KB = 4;
+  static constexpr int KB = 2;
   static constexpr int TB = TS * KB;         // big tile (bbox, histogram)
   static constexpr int UB = 4;               // points per thread per load batch of a big tile
   static constexpr int W = RADIX_;
@@ -361,6 +361,7 @@ struct Cfg {
   static_assert(MAXP <= kMaxPassSlots, "pass slots");
   static_assert(SI <= 32 && RI <= 32, "item masks are 32-bit");
   static_assert(TB % (BLOCK * UB) == 0, "big tile = whole load batches");
+  static_assert(TR <= 8192, "reduce tile: 16-bit item positions, 21-bit colour sums");
 
   struct SortSmem {
     uint32_t lo[TS];
@@ -384,6 +385,8 @@ struct Cfg {
     uint32_t klo[TR];
     uint32_t khi[TR];
     uint32_t kid[TR];
+    uint16_t hpos[TR];   // tile item of the r-th head of the tile
+    uint32_t has_prev, prev_lo, prev_hi, has_next, next_lo, next_hi;
     uint32_t wsum[NW];
     Seg wtot[NW];
     uint64_t excl;
@@ -410,6 +413,7 @@ struct SmemOf {
 
 // Control state of a workgroup, written by thread 0 and read by all.
 constexpr int kLdsFrames = 256;  // calls with at most this many frames keep tile prefixes in LDS
+constexpr int kFpCache = 64;     // ... and this many, every frame's grid parameters
 
 struct BlockCtl {
   uint32_t item;
@@ -421,6 +425,13 @@ struct BlockCtl {
   FrameParams fp;
   FrameDesc fd;
   uint32_t tp[3][kLdsFrames + 1];    // big / sort / reduce tile prefixes over frames
+  uint32_t ilv_s[kIlvMaxRounds + 1];
+  uint32_t ilv_perm[kIlvMaxFrames];
+  int32_t ilv_rounds;                // rounds of the round-robin sort order (0: frame order)
+  uint32_t ilv_total;                // items of a one-pass launch's own order
+  int32_t cached;                    // one-phase launches after the bbox: every frame below
+  FrameParams fpa[kFpCache];
+  FrameDesc fda[kFpCache];
 };
 
 template <class C>
@@ -622,6 +633,15 @@ __device__ void sort_tile(const Ws& ws, const Io& io, typename C::SortSmem& S, c
   const int shift = p * f.w;
   const int64_t t0 = (int64_t)j * C::TS;
   const int t = fd.ts0 + j;
+  if (p > 0 && t0 >= (int64_t)f.n_valid) {
+    // past the frame's valid points (only later tiles of the frame, which no
+    // tile looks back at)
+    if (threadIdx.x == 0) {
+      if (persistent) fence_rel();
+      atomicAdd(&ws.fs[b].pass_done[p], 1u);
+    }
+    return;
+  }
 
   // frame-wide digit offsets of this pass
   {
@@ -970,10 +990,23 @@ __device__ void fix_tile(const Ws& ws, const Io& io, int t, int key_mode, uint32
   }
 }
 
+// Key, first index and corner of the cell whose first point is item `li` of
+// the tile (keys and indices are in LDS; the corner is decoded from the key).
+template <class C>
+__device__ __forceinline__ CellOut cell_at(const typename C::RedSmem& S, const FrameParams& f,
+                                           int key_mode, int li) {
+  CellOut c;
+  c.lo = S.klo[li];
+  c.hi = f.wide ? S.khi[li] : 0u;
+  c.ref = S.kid[li];
+  corner_of_key(f, key_mode, c.lo, c.hi, c.r);
+  return c;
+}
+
 template <class C>
 __device__ void red_tile(const Ws& ws, const Io& io, typename C::RedSmem& S, const FrameDesc& fd,
                          int b, int j, const FrameParams& f, int key_mode, uint32_t want, int B,
-                         int NTr, int64_t N) {
+                         int NTr, int64_t N, bool persistent) {
   constexpr int K = C::RI;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int t = fd.tr0 + j;
@@ -987,26 +1020,44 @@ __device__ void red_tile(const Ws& ws, const Io& io, typename C::RedSmem& S, con
   const uint32_t* kid = ws.idx[fb] + fd.off;
   const int base = threadIdx.x * K;
   const uint32_t Nm1 = (uint32_t)(N - 1);
+  if (cnt == 0) {
+    // past the frame's valid points: only the row count chain goes on
+    if (threadIdx.x == 0) {
+      uint64_t excl = 0;
+      if (t == 0) {
+        st_rlx64(&ws.rdesc[0], kFlagP64);
+      } else {
+        st_rlx64(&ws.rdesc[t], kFlagA64);
+        excl = look_back64(ws.rdesc, t - 1, ws.ctl);
+        st_rlx64(&ws.rdesc[t], kFlagP64 | excl);
+      }
+      if (j == 0) {
+        io.out_offsets[b] = (int64_t)excl;
+        io.frame_status[b] = ld_rlx(&ws.ctl->error) ? 5 : f.status;
+      }
+      if (t == NTr - 1) io.out_offsets[B] = (int64_t)excl;
+    }
+    return;
+  }
 
-  // ---- keys, indices, gathered points (blocked: thread i owns items i*K .. i*K+K-1)
-  uint32_t lo_[K], hi_[K], id_[K];
+  // ---- keys and indices to LDS, gathered points to registers
+  // (blocked: thread i owns items i*K .. i*K+K-1 of the tile)
   float px[K], py[K], pz[K];
   uint32_t c24[K];
-  uint32_t vmask = 0, hmask = 0;
-  uint32_t plo = 0, phi = 0, next_lo = 0, next_hi = 0;
-  bool have_prev = false;
-  if (cnt > 0) {
+  {
     const int64_t lastp = e0 - 1;
-    const int64_t pp = min(max(s0 + base - 1, (int64_t)0), lastp);
-    plo = klo[pp];
-    phi = f.wide ? khi[pp] : 0u;
-    have_prev = base < cnt && s0 + base > 0;
+    uint32_t id_[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) {
       const int64_t pos = min(s0 + base + i, lastp);
-      lo_[i] = klo[pos];
-      hi_[i] = f.wide ? khi[pos] : 0u;
+      const uint32_t lo = klo[pos];
+      const uint32_t hi = f.wide ? khi[pos] : 0u;
       id_[i] = min(kid[pos], Nm1);
+      if (base + i < cnt) {
+        S.klo[base + i] = lo;
+        if (f.wide) S.khi[base + i] = hi;
+        S.kid[base + i] = id_[i];
+      }
     }
 #pragma unroll
     for (int i = 0; i < K; ++i) {
@@ -1016,27 +1067,42 @@ __device__ void red_tile(const Ws& ws, const Io& io, typename C::RedSmem& S, con
       pz[i] = r4.z;
       c24[i] = __float_as_uint(r4.w);
     }
-    if (threadIdx.x == C::BLOCK - 1 && s0 + C::TR < nv) {
-      next_lo = klo[s0 + C::TR];
-      next_hi = f.wide ? khi[s0 + C::TR] : 0u;
-    }
+  }
+  if (threadIdx.x == 0) {
+    // the keys just before and just after the tile
+    S.has_prev = s0 > 0 ? 1u : 0u;
+    S.prev_lo = s0 > 0 ? klo[s0 - 1] : 0u;
+    S.prev_hi = (s0 > 0 && f.wide) ? khi[s0 - 1] : 0u;
+    S.has_next = e0 < nv ? 1u : 0u;
+    S.next_lo = e0 < nv ? klo[e0] : 0u;
+    S.next_hi = (e0 < nv && f.wide) ? khi[e0] : 0u;
+  }
+  __syncthreads();
+
+  // ---- head flags: an item starts a cell when its key differs from the previous one
+  uint32_t vmask = 0, hmask = 0;
 #pragma unroll
-    for (int i = 0; i < K; ++i) {
-      if (base + i < cnt) {
-        S.klo[base + i] = lo_[i];
-        S.khi[base + i] = hi_[i];
-        S.kid[base + i] = id_[i];
-        vmask |= 1u << i;
-        const bool head = !have_prev || lo_[i] != plo || hi_[i] != phi;
-        if (head) hmask |= 1u << i;
-        plo = lo_[i];
-        phi = hi_[i];
-        have_prev = true;
+  for (int i = 0; i < K; ++i) {
+    const int li = base + i;
+    if (li < cnt) {
+      vmask |= 1u << i;
+      bool head;
+      if (li == 0) {
+        head = !S.has_prev || S.klo[0] != S.prev_lo || (f.wide && S.khi[0] != S.prev_hi);
+      } else {
+        head = S.klo[li] != S.klo[li - 1] || (f.wide && S.khi[li] != S.khi[li - 1]);
       }
+      if (head) hmask |= 1u << i;
     }
   }
   uint32_t H;
   const uint32_t hb = block_excl_scan<C::BLOCK>((uint32_t)__popc(hmask), S.wsum, H);
+  {
+    uint32_t r = hb;
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+      if ((hmask >> i) & 1u) S.hpos[r++] = (uint16_t)(base + i);
+  }
 
   // ---- global look-back over head counts: dense rows across frames
   if (threadIdx.x == 0) {
@@ -1063,11 +1129,7 @@ __device__ void red_tile(const Ws& ws, const Io& io, typename C::RedSmem& S, con
   acc_zero(pre);
   acc_zero(cur);
   bool seen_head = false;
-  uint32_t cur_hp = 0, lh = 0;
-  CellOut cur_c, pre_c;
-  cur_c.lo = cur_c.hi = cur_c.ref = 0;
-  pre_c = cur_c;
-  for (int i = 0; i < 3; ++i) cur_c.r[i] = pre_c.r[i] = 0.f;
+  uint32_t lh = 0;
 #pragma unroll
   for (int i = 0; i < K; ++i) {
     if (!((vmask >> i) & 1u)) continue;
@@ -1080,30 +1142,21 @@ __device__ void red_tile(const Ws& ws, const Io& io, typename C::RedSmem& S, con
         pre = cur;
         seen_head = true;
       } else {
-        // a segment that opened and closed inside this thread
-        finalize_row(io, want, excl_t + hb + lh - 1, N, cur, nullptr, cur_c);
+        // a cell that opened and closed inside this thread
+        finalize_row(io, want, excl_t + hb + lh - 1, N, cur, nullptr,
+                     cell_at<C>(S, f, key_mode, S.hpos[hb + lh - 1]));
       }
       acc_zero(cur);
       ++lh;
-      cur_hp = (uint32_t)(s0 + base + i);
-      cur_c.lo = lo_[i];
-      cur_c.hi = hi_[i];
-      cur_c.ref = id_[i];
-      for (int a = 0; a < 3; ++a) cur_c.r[a] = r[a];
-    } else if (!seen_head && cur.n == 0) {
-      pre_c.lo = lo_[i];
-      pre_c.hi = hi_[i];
-      for (int a = 0; a < 3; ++a) pre_c.r[a] = r[a];
     }
     acc_add(cur, dv, c24[i]);
-    if (want & kOutPointCell) io.point_cell[id_[i]] = (int32_t)(excl_t + hb + lh - 1);
+    if (want & kOutPointCell) io.point_cell[S.kid[base + i]] = (int32_t)(excl_t + hb + lh - 1);
   }
   if (!seen_head) pre = cur;
 
   // ---- block segmented scan of the threads' open ends
   Seg mine;
   mine.f = seen_head ? 1u : 0u;
-  mine.hp = seen_head ? cur_hp : 0u;
   mine.a = seen_head ? cur : pre;
   Seg incl = mine;
 #pragma unroll
@@ -1115,64 +1168,36 @@ __device__ void red_tile(const Ws& ws, const Io& io, typename C::RedSmem& S, con
   __syncthreads();
   Seg wp;
   wp.f = 0;
-  wp.hp = 0;
   acc_zero(wp.a);
   for (int i = 0; i < w; ++i) wp = seg_combine(wp, S.wtot[i]);
   Seg ex = seg_shfl_up(incl, 1);
   if (lane == 0) {
     ex.f = 0;
-    ex.hp = 0;
     acc_zero(ex.a);
   }
   ex = seg_combine(wp, ex);
 
-  // (i) the segment open at this thread's start closes at its first head
+  // (i) the cell open at this thread's start closes at its first head
   if (seen_head) {
     Acc tot = ex.a;
     acc_merge(tot, pre);
     if (tot.n > 0) {
-      CellOut c = pre_c;  // key/corner from any member
-      if (pre.n == 0) {
-        // all of its members sit before this thread: take the key from LDS
-        const int lp = ex.f ? (int)(ex.hp - (uint32_t)s0) : 0;
-        c.lo = S.klo[lp];
-        c.hi = S.khi[lp];
-        corner_of_key(f, key_mode, c.lo, c.hi, c.r);
-      }
       if (ex.f) {
-        c.ref = S.kid[ex.hp - (uint32_t)s0];
-        finalize_row(io, want, excl_t + hb - 1, N, tot, nullptr, c);
+        // its first point is the last head before this thread
+        finalize_row(io, want, excl_t + hb - 1, N, tot, nullptr,
+                     cell_at<C>(S, f, key_mode, S.hpos[hb - 1]));
       } else {
-        // opened in an earlier tile: the fix-up phase adds the earlier parts
-        write_pend(ws, t, b, j, tot, c, excl_t - 1);
+        // opened in an earlier tile (the tile's first item is one of its
+        // points): the fix-up phase adds the earlier parts
+        write_pend(ws, t, b, j, tot, cell_at<C>(S, f, key_mode, 0), excl_t - 1);
       }
     }
   }
-  // (ii) the thread holding the tile's last item closes or hands on the last segment
-  if (cnt > 0 && base < cnt && base + K >= cnt) {
+  // (ii) the thread holding the tile's last item closes or hands on the last cell
+  if (base < cnt && base + K >= cnt) {
     const Seg last = seg_combine(ex, mine);
-    const int li = cnt - 1 - base;
-    const int64_t e = s0 + cnt;
-    bool cont = false;
-    uint32_t llo = 0, lhi = 0, lid = 0;
-    float lp[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-    for (int i = 0; i < K; ++i) {
-      if (i == li) {
-        llo = lo_[i];
-        lhi = hi_[i];
-        lid = id_[i];
-        lp[0] = px[i];
-        lp[1] = py[i];
-        lp[2] = pz[i];
-      }
-    }
-    if (e < nv) cont = next_lo == llo && (!f.wide || next_hi == lhi);
-    CellOut c;
-    c.lo = llo;
-    c.hi = lhi;
-    c.ref = lid;
-    corner_of(f, lp, c.r);
+    const int ll = cnt - 1;
+    const bool cont = S.has_next && S.next_lo == S.klo[ll] && (!f.wide || S.next_hi == S.khi[ll]);
     if (cont) {
       Frag fr;
       fr.n = last.a.n;
@@ -1180,21 +1205,23 @@ __device__ void red_tile(const Ws& ws, const Io& io, typename C::RedSmem& S, con
         fr.s[a] = last.a.s[a];
         fr.c[a] = last.a.c[a];
       }
-      fr.head_pos = last.f ? last.hp : kNoHead;
-      fr.ref = last.f ? S.kid[last.hp - (uint32_t)s0] : 0u;
+      const int hl = last.f ? (int)S.hpos[H - 1] : 0;
+      fr.head_pos = last.f ? (uint32_t)(s0 + hl) : kNoHead;
+      fr.ref = last.f ? S.kid[hl] : 0u;
       fr.pad = 0;
       fr.rgb = last.a.rgb;
       ws.frag[t] = fr;
-      fence_rel();
-      st_rlx(&ws.fflag[t], 1u);
+      if (persistent) {  // one-phase launches hand the parts on at the kernel boundary
+        fence_rel();
+        st_rlx(&ws.fflag[t], 1u);
+      }
     } else if (last.f) {
-      c.ref = S.kid[last.hp - (uint32_t)s0];
-      finalize_row(io, want, excl_t + (int64_t)H - 1, N, last.a, nullptr, c);
+      finalize_row(io, want, excl_t + (int64_t)H - 1, N, last.a, nullptr,
+                   cell_at<C>(S, f, key_mode, S.hpos[H - 1]));
     } else {
-      write_pend(ws, t, b, j, last.a, c, excl_t - 1);
+      write_pend(ws, t, b, j, last.a, cell_at<C>(S, f, key_mode, 0), excl_t - 1);
     }
   }
-
 }
 
 // ---------------------------------------------------------- pipeline ----
@@ -1245,7 +1272,16 @@ __device__ __forceinline__ void next_item(const Ws& ws, const CallHdr& hdr, Bloc
     }
     const uint32_t tiling = ph <= C::PH_HIST ? 0u : (ph == C::PH_RED ? 2u : 1u);
     int b, j;
-    if (hdr.B <= kLdsFrames) {
+    if (tiling == 1 && bc.ilv_rounds > 0) {
+      int lo = 0, hi = bc.ilv_rounds;  // largest round r with ilv_s[r] <= t
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((int)bc.ilv_s[mid] <= t) lo = mid;
+        else hi = mid;
+      }
+      b = (int)bc.ilv_perm[t - (int)bc.ilv_s[lo]];
+      j = lo;
+    } else if (hdr.B <= kLdsFrames) {
       const uint32_t* tp = bc.tp[tiling];
       int lo = 0, hi = hdr.B;  // largest b with tp[b] <= t
       while (hi - lo > 1) {
@@ -1261,7 +1297,11 @@ __device__ __forceinline__ void next_item(const Ws& ws, const CallHdr& hdr, Bloc
       b = (int)ti.x;
       j = (int)ti.y;
     }
-    if (bc.fd_b != b) {
+    if (bc.cached) {
+      bc.fd = bc.fda[b];
+      bc.fp = bc.fpa[b];
+      bc.fd_b = bc.fp_b = b;
+    } else if (bc.fd_b != b) {
       bc.fd = ws.fd[b];
       bc.fd_b = b;
     }
@@ -1287,12 +1327,13 @@ __device__ __forceinline__ void next_item(const Ws& ws, const CallHdr& hdr, Bloc
       if (p >= f.passes) {
         // no work for this frame in this pass: jump the queue past it, or past
         // every remaining pass once no frame needs this one
-        uint32_t jump = base + (uint32_t)(fd.ts0 + fd.nts);
+        // (in round-robin order a frame's tiles are not contiguous: skip one)
+        uint32_t jump = bc.ilv_rounds > 0 ? 0u : base + (uint32_t)(fd.ts0 + fd.nts);
         const bool all_hist = wait_geq(&ws.ctl->hist_tiles_done, (uint32_t)hdr.NTb, ws.ctl);
         if (persistent) fence_acq();
         if (all_hist && (uint32_t)p >= ld_rlx(&ws.ctl->max_passes))
           jump = persistent ? 2 * nb + C::MAXP * ns : total;
-        atomicMax(counter, jump);
+        if (jump) atomicMax(counter, jump);
         continue;
       }
       if (bc.dep_b[ph] != b) {
@@ -1346,6 +1387,54 @@ __global__ __launch_bounds__(C::BLOCK) void vg_pipeline_kernel(Ws ws, int ph_lo,
       bc.tp[2][i] = ws.tpr[i];
     }
   }
+  if (hdr.ilv_rounds > 0) {
+    for (int i = threadIdx.x; i <= hdr.ilv_rounds; i += C::BLOCK) bc.ilv_s[i] = ws.ilv_s[i];
+    for (int i = threadIdx.x; i < hdr.B; i += C::BLOCK) bc.ilv_perm[i] = ws.ilv_perm[i];
+  }
+  // a one-phase launch after the bbox pass: every frame's grid is final
+  const bool cache = !persistent && ph_lo != C::PH_BBOX && hdr.B <= kFpCache;
+  if (cache) {
+    for (int i = threadIdx.x; i < hdr.B; i += C::BLOCK) {
+      bc.fda[i] = ws.fd[i];
+      bc.fpa[i] = frame_params(ws, i, hdr.key_mode, C::W);
+    }
+  }
+  if (threadIdx.x == 0) {
+    bc.cached = cache ? 1 : 0;
+    bc.ilv_rounds = hdr.ilv_rounds;
+  }
+  // a one-pass radix launch with every frame's grid at hand orders its tiles
+  // round-robin over just the frames that need this pass
+  const bool own_order = cache && ph_lo >= C::PH_SORT0 && ph_lo < C::PH_RED &&
+                         hdr.ilv_rounds > 0 && hdr.B <= kIlvMaxFrames;
+  if (own_order) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int p = ph_lo - C::PH_SORT0;
+      int nf = 0, rounds = 0;
+      for (int fb = 0; fb < hdr.B; ++fb) {
+        if (bc.fpa[fb].passes <= p) continue;
+        // insertion by descending sort-tile count, frame order among equals
+        const int nt = bc.fda[fb].nts;
+        int k = nf++;
+        while (k > 0 && bc.fda[bc.ilv_perm[k - 1]].nts < nt) {
+          bc.ilv_perm[k] = bc.ilv_perm[k - 1];
+          --k;
+        }
+        bc.ilv_perm[k] = (uint32_t)fb;
+        rounds = max(rounds, nt);
+      }
+      rounds = min(rounds, kIlvMaxRounds);
+      int c = nf;
+      bc.ilv_s[0] = 0;
+      for (int r = 0; r < rounds; ++r) {
+        while (c > 0 && bc.fda[bc.ilv_perm[c - 1]].nts <= r) --c;
+        bc.ilv_s[r + 1] = bc.ilv_s[r] + (uint32_t)c;
+      }
+      bc.ilv_rounds = rounds;
+      bc.ilv_total = bc.ilv_s[rounds];
+    }
+  }
   if (threadIdx.x == 0) {
     bc.fp_b = -1;
     bc.fd_b = -1;
@@ -1357,6 +1446,7 @@ __global__ __launch_bounds__(C::BLOCK) void vg_pipeline_kernel(Ws ws, int ph_lo,
       bc.item = total;
   }
   __syncthreads();
+  if (own_order) total = bc.ilv_total;
   if (bc.item >= total && total > 0) return;
   for (;;) {
     if (threadIdx.x == 0) next_item<C>(ws, hdr, bc, counter, persistent, ph_lo, total);
@@ -1382,11 +1472,14 @@ __global__ __launch_bounds__(C::BLOCK) void vg_pipeline_kernel(Ws ws, int ph_lo,
           sort_tile<C>(ws, io, sm.sort, fd, b, j, ph - C::PH_SORT0, f, hdr.key_mode, persistent);
       } else {
         if constexpr (KIND == kAll || KIND == kRed) {
-          red_tile<C>(ws, io, sm.red, fd, b, j, f, hdr.key_mode, hdr.want, hdr.B, hdr.NTr, hdr.N);
-          __syncthreads();
-          if (threadIdx.x == 0) {
-            if (persistent) fence_rel();
-            atomicAdd(&ws.ctl->red_tiles_done, 1u);
+          red_tile<C>(ws, io, sm.red, fd, b, j, f, hdr.key_mode, hdr.want, hdr.B, hdr.NTr, hdr.N,
+                      persistent);
+          if (persistent) {
+            __syncthreads();
+            if (threadIdx.x == 0) {
+              fence_rel();
+              atomicAdd(&ws.ctl->red_tiles_done, 1u);
+            }
           }
         }
       }

@@ -94,7 +94,9 @@ def test_workspace_bytes():
 def test_tunings():
     t = vg.default_tuning()
     assert vg.tuning_supported(t)
-    assert not vg.tuning_supported(vg.default_tuning(reduce_block=512))  # blocks must match
+    t2 = vg.default_tuning()
+    t2.reduce_block = t2.sort_block * 2
+    assert not vg.tuning_supported(t2)  # one block size for every phase
     assert not vg.tuning_supported(vg.default_tuning(sort_items=5))
     assert not vg.tuning_supported(vg.default_tuning(exec_mode=3))
     bad = vg.default_tuning(sort_items=5)
