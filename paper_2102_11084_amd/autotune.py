@@ -1,0 +1,109 @@
+"""Autotuner for libvg on one GPU: picks block size, items per thread, radix
+digit width, launch form and workgroups per CU for a workload.
+
+Every candidate built into the library is run on the workload (seeded
+synthetic RGB-D frames, see datagen.batch); its cell keys, counts and rows
+must equal the first candidate's bit for bit, else it is rejected.  The
+fastest candidate (median of timed runs, HIP events on the stream) is written
+as JSON, which bench.py and vg.load_tuning read.
+
+  python -m paper_2102_11084_amd.autotune [--frames 64] [--out tuning_gfx950.json]
+"""
+from __future__ import annotations
+
+import argparse
+import itertools
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_OUT = os.path.join(HERE, "tuning_gfx950.json")
+
+# (block, sort items per thread, radix bits, reduce items per thread) to try;
+# candidates the library was not built with are skipped.
+SHAPES = [(256, 16, 8, 8), (256, 8, 8, 8), (256, 12, 8, 8), (256, 16, 8, 4), (256, 16, 7, 8),
+          (512, 8, 8, 4), (512, 8, 8, 8), (256, 16, 6, 8), (256, 8, 8, 4)]
+MODES = (0, 1)          # persistent, phased
+BLOCKS_PER_CU = (0,)    # 0 = occupancy limit
+
+
+def candidates(vg):
+    out = []
+    for (blk, si, rb, ri), mode, bpc in itertools.product(SHAPES, MODES, BLOCKS_PER_CU):
+        t = vg.default_tuning(sort_block=blk, sort_items=si, radix_bits=rb, reduce_block=blk,
+                              reduce_items=ri, exec_mode=mode, blocks_per_cu=bpc)
+        if vg.tuning_supported(t):
+            out.append(t)
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--frames", type=int, default=64)
+    ap.add_argument("--reps", type=int, default=7)
+    ap.add_argument("--out", default=DEFAULT_OUT)
+    args = ap.parse_args(argv)
+
+    sys.path.insert(0, os.path.dirname(HERE))
+    import torch
+
+    from paper_2102_11084_amd import datagen as dg
+    from paper_2102_11084_amd import vg
+
+    dev = torch.device("cuda:0")
+    x, y, z, rgb, offs, leaves = dg.batch(args.frames)
+    N = int(offs[-1])
+    d = [torch.from_numpy(a).to(dev) for a in (x, y, z, rgb.reshape(-1))]
+    outputs = ("xyz", "rgb", "count", "key")
+    stream = torch.cuda.current_stream(dev)
+    ref = None
+    results = []
+    for t in candidates(vg):
+        plan = vg.BatchPlan(len(leaves), N, vg.KEY_LINEAR, t, use_graph=True)
+        outs = plan.alloc_outputs(N, len(leaves), dev, outputs=outputs)
+        for _ in range(2):
+            plan.run(*d, offs, leaves, out=outs)
+        torch.cuda.synchronize()
+        m = int(outs[0]["out_offsets"][-1].item())
+        sig = (outs[0]["key"][:m].cpu().numpy().tobytes(), outs[0]["count"][:m].cpu().numpy().tobytes(),
+               outs[0]["out_offsets"].cpu().numpy().tobytes())
+        ok = True
+        if ref is None:
+            ref = sig
+        elif sig != ref:
+            ok = False
+        times = []
+        for _ in range(args.reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            plan.run(*d, offs, leaves, out=outs)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        plan.close()
+        ms = float(np.median(times))
+        results.append((ms, ok, t.as_dict()))
+        print(f"[autotune] {t.as_dict()} {ms:.3f} ms {'ok' if ok else 'MISMATCH'}", flush=True)
+    good = sorted([r for r in results if r[1]], key=lambda r: r[0])
+    best = good[0]
+    doc = {
+        "tuning": best[2],
+        "workload": f"batched: {len(leaves)} uneven RGB-D frames ({N} points)",
+        "median_ms": round(best[0], 4),
+        "mpoints_s": round(N / (best[0] * 1e-3) / 1e6, 1),
+        "device": torch.cuda.get_device_name(dev),
+        "when": time.strftime("%Y-%m-%d %H:%M:%S"),
+        "candidates": [{"tuning": r[2], "median_ms": round(r[0], 4), "identical_cells": r[1]}
+                       for r in sorted(results, key=lambda r: r[0])],
+    }
+    with open(args.out, "w") as f:
+        json.dump(doc, f, indent=1)
+    print(f"[autotune] best {best[2]} {best[0]:.3f} ms -> {args.out}", flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -429,6 +429,7 @@ struct BlockCtl {
   uint32_t ilv_perm[kIlvMaxFrames];
   int32_t ilv_rounds;                // rounds of the round-robin sort order (0: frame order)
   uint32_t ilv_total;                // items of a one-pass launch's own order
+  uint32_t scan_w[32];               // block scan scratch
   int32_t cached;                    // one-phase launches after the bbox: every frame below
   FrameParams fpa[kFpCache];
   FrameDesc fda[kFpCache];
@@ -1408,31 +1409,44 @@ __global__ __launch_bounds__(C::BLOCK) void vg_pipeline_kernel(Ws ws, int ph_lo,
   const bool own_order = cache && ph_lo >= C::PH_SORT0 && ph_lo < C::PH_RED &&
                          hdr.ilv_rounds > 0 && hdr.B <= kIlvMaxFrames;
   if (own_order) {
+    // keep the host order (frames by descending sort-tile count) of just the
+    // frames that need this pass, then count the frames of every round
     __syncthreads();
-    if (threadIdx.x == 0) {
-      const int p = ph_lo - C::PH_SORT0;
-      int nf = 0, rounds = 0;
-      for (int fb = 0; fb < hdr.B; ++fb) {
-        if (bc.fpa[fb].passes <= p) continue;
-        // insertion by descending sort-tile count, frame order among equals
-        const int nt = bc.fda[fb].nts;
-        int k = nf++;
-        while (k > 0 && bc.fda[bc.ilv_perm[k - 1]].nts < nt) {
-          bc.ilv_perm[k] = bc.ilv_perm[k - 1];
-          --k;
-        }
-        bc.ilv_perm[k] = (uint32_t)fb;
-        rounds = max(rounds, nt);
-      }
-      rounds = min(rounds, kIlvMaxRounds);
-      int c = nf;
-      bc.ilv_s[0] = 0;
-      for (int r = 0; r < rounds; ++r) {
-        while (c > 0 && bc.fda[bc.ilv_perm[c - 1]].nts <= r) --c;
-        bc.ilv_s[r + 1] = bc.ilv_s[r] + (uint32_t)c;
-      }
+    const int p = ph_lo - C::PH_SORT0;
+    const int i = threadIdx.x;
+    const uint32_t fr = (i < hdr.B) ? bc.ilv_perm[i] : 0u;
+    const uint32_t keep = (i < hdr.B && bc.fpa[fr].passes > p) ? 1u : 0u;
+    uint32_t nkeep;
+    const uint32_t pos = block_excl_scan<C::BLOCK>(keep, bc.scan_w, nkeep);
+    if (keep) bc.tp[0][pos] = fr;  // the big-tile prefixes are not used by radix launches
+    __syncthreads();
+    const int rounds = nkeep ? bc.fda[bc.tp[0][0]].nts : 0;  // the first frame has the most
+    // cnt(r) = kept frames with more than r tiles; ilv_s = exclusive prefix of cnt
+    constexpr int PER = (kIlvMaxRounds + C::BLOCK - 1) / C::BLOCK;
+    uint32_t cnts[PER];
+    uint32_t mysum = 0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int r = i * PER + q;
+      uint32_t c = 0;
+      if (r < rounds)
+        for (uint32_t k = 0; k < nkeep; ++k) c += (bc.fda[bc.tp[0][k]].nts > r) ? 1u : 0u;
+      cnts[q] = c;
+      mysum += c;
+    }
+    uint32_t total_items;
+    uint32_t run = block_excl_scan<C::BLOCK>(mysum, bc.scan_w, total_items);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int r = i * PER + q;
+      if (r < rounds) bc.ilv_s[r] = run;
+      run += cnts[q];
+    }
+    for (int k = i; k < (int)nkeep; k += C::BLOCK) bc.ilv_perm[k] = bc.tp[0][k];
+    if (i == 0) {
+      bc.ilv_s[rounds] = total_items;
       bc.ilv_rounds = rounds;
-      bc.ilv_total = bc.ilv_s[rounds];
+      bc.ilv_total = total_items;
     }
   }
   if (threadIdx.x == 0) {
