@@ -2,11 +2,12 @@
 """Voxel-grid downsampling throughput on one MI355X (libvg).
 
 Step = one batched call over the uneven 64-frame RGB-D batch (every frame
-through bbox, histogram, radix sort and segmented reduce, one persistent
-launch replayed from a hipGraph), inputs resident in HBM.  Prints one JSON
+through bbox, histogram, radix sort and segmented reduce; the call's launch
+sequence replayed from a hipGraph), inputs resident in HBM.  Prints one JSON
 line: Mpoints/s (input points, valid and invalid), the roofline of the
-pipeline kernel, the plain per-frame path and the backward on the same GPU,
-and the CPU oracle on a bounded sample.
+dominant kernel (HIP event pairs around each launch, in a second timed region
+of the same steps), the whole step's roofline, the plain per-frame path and the
+backward on the same GPU, and the CPU oracle on a bounded sample.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -57,6 +58,70 @@ def algorithmic_bytes(n, nv, passes, m, point_cell=False):
     return 24 * n + (8 + 4 + 16 * passes + 8 + 15 + (4 if point_cell else 0)) * nv + 27 * m
 
 
+def kernel_bytes(n, nv, passes, m, point_cell=False):
+    """Algorithmic bytes per step of each kernel of the phased pipeline, summed
+    over frames (lists indexed like the frames):
+      bbox    reads xyz of every point                      12 B x n
+      hist    reads xyz of every point to form the keys      12 B x n
+      sort    pass 0 reads xyz, writes (key, index) pairs    12 B x n + 8 B x n_v
+              pass p > 0 reads and writes the pairs          16 B x n_v of frames with > p passes
+      reduce  reads the pairs, gathers xyz + rgb             23 B x n_v (+4 B x n_v point rows)
+              writes xyz, rgb, count, key per cell           27 B x m
+    """
+    n, nv, passes, m = (np.asarray(a, dtype=np.int64) for a in (n, nv, passes, m))
+    live = passes > 0
+    sort = int((12 * n).sum() + (8 * nv[live]).sum() + (16 * nv * np.maximum(passes - 1, 0)).sum())
+    red = int(((23 + (4 if point_cell else 0)) * nv).sum() + (27 * m).sum())
+    b = {"init": 0, "bbox": int(12 * n.sum()), "hist": int(12 * n.sum()), "sort": sort,
+         "reduce": red, "fixup": 0}
+    b["pipeline"] = sum(b.values())
+    return b
+
+
+def source_digest():
+    """Digest of the device code, the header and the tuning file: counter
+    figures taken under another digest no longer describe these kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    files = [os.path.join(ROOT, "include", "vg.h"),
+             os.path.join(ROOT, "paper_2102_11084_amd", "tuning_gfx950.json")]
+    csrc = os.path.join(ROOT, "paper_2102_11084_amd", "csrc")
+    files += [os.path.join(csrc, f) for f in sorted(os.listdir(csrc))
+              if f.endswith((".hip", ".hpp", ".h"))]
+    for f in files:
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kind, workload_tag):
+    """HBM bytes per launch of `kind` from the committed counter summary, or
+    None when it is missing or was taken on other kernels."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload_tag}.txt")
+    try:
+        rows = dict(line.split(":", 1) for line in open(path) if ":" in line and not line.startswith("#"))
+    except OSError:
+        return None, "no counter summary"
+    rows = {k.strip(): v.strip() for k, v in rows.items()}
+    if rows.get("source_digest") != source_digest():
+        return None, "counter summary taken on other kernels"
+    v = rows.get(f"{kind}_bytes_per_launch")
+    return (int(float(v)), path) if v else (None, f"no {kind} row")
+
+
+def copy_calibration(steps):
+    """A plain device copy of known size, for scaling FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(steps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": steps}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,12 +139,20 @@ def main():
     ap.add_argument("--no-legs", action="store_true", help="skip plain/backward legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--kernel-steps", type=int, default=10,
+                    help="steps of the per-kernel event timing region")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (frames shard across GPUs by design, "
               "but no multi-GPU path is built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration(max(args.steps, 1))
+        return
 
     import torch
 
@@ -136,8 +209,35 @@ def main():
                                     z[offs[b]:offs[b + 1]], leaves[b], radix) for b in range(len(leaves))])
     alg = sum(algorithmic_bytes(int(offs[b + 1] - offs[b]), int(nv_frames[b]), int(passes[b]),
                                 int(m_frames[b]), args.point_cell) for b in range(len(leaves)))
-    achieved = alg / (ev_ms * 1e-3) / 1e9
+    step_achieved = alg / (ev_ms * 1e-3) / 1e9
     floor_bytes = 15 * int(nv_frames.sum()) + 27 * int(m_frames.sum())
+
+    # per-kernel timing region: the same step, launched directly with a HIP
+    # event pair on the plan's stream around every kernel
+    plan.set_timing(True)
+    per_kind, launches = {}, {}
+    for _ in range(max(args.kernel_steps, 1)):
+        plan.run(*d, offs, leaves, out=outs)
+        for kind, ms in plan.kernel_times():
+            per_kind[kind] = per_kind.get(kind, 0.0) + ms
+            launches[kind] = launches.get(kind, 0) + 1
+    plan.set_timing(False)
+    ks = max(args.kernel_steps, 1)
+    kb = kernel_bytes(np.diff(offs), nv_frames, passes, m_frames, args.point_cell)
+    kinds = {k: {"ms_per_step": round(v / ks, 4), "launches_per_step": launches[k] // ks,
+                 "avg_launch_ms": round(v / launches[k], 4),
+                 "algorithmic_bytes_per_step": kb[k],
+                 "gbs": round(kb[k] / (v / ks * 1e-3) / 1e9, 1) if v > 0 else None}
+             for k, v in per_kind.items()}
+    dom = max(per_kind, key=lambda k: per_kind[k])
+    dom_ms = per_kind[dom] / launches[dom]
+    dom_bytes = kb[dom] / (launches[dom] // ks)
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    tag = f"batch{len(leaves)}"
+    traffic, tsrc = read_traffic(dom, tag)
+    log(f"kernels per step: " + ", ".join(f"{k} {v['ms_per_step']:.3f} ms x{v['launches_per_step']}"
+                                          f" ({v['gbs']} GB/s)" for k, v in kinds.items()))
+    log(f"dominant kernel: {dom}, {dom_ms:.4f} ms/launch, {achieved:.1f} GB/s; traffic: {tsrc}")
     result = {
         "metric": METRIC, "value": round(value, 2), "unit": "Mpoints/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -153,12 +253,17 @@ def main():
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "vg_pipeline_kernel (persistent)",
-            "algorithmic_bytes_per_launch": int(alg),
-            "kernel_ms_events": round(ev_ms, 4),
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": f"vg_pipeline_kernel<{dom}>",
+            "algorithmic_bytes_per_launch": int(dom_bytes),
+            "avg_launch_ms_events": round(dom_ms, 4),
+        },
+        "step_roofline": {
+            "algorithmic_bytes": int(alg), "achieved": round(step_achieved, 1),
+            "frac": round(step_achieved / HBM_PEAK_GBS, 4),
             "floor_frac": round(floor_bytes / (ev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         },
+        "kernels": kinds,
     }
 
     if not args.no_legs:

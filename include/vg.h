@@ -57,8 +57,10 @@ typedef enum vg_key_mode { VG_KEY_LINEAR = 0, VG_KEY_MORTON = 1 } vg_key_mode;
 
 /* How the pipeline is launched.  PERSISTENT: one kernel whose workgroups take
  * tiles of every phase from a work queue ordered so that a tile only waits on
- * tiles dequeued before it.  PHASED: one launch per phase (same device code),
- * used to time each phase on its own. */
+ * tiles dequeued before it.  PHASED: one launch per phase, each with a kernel
+ * compiled for that phase alone (fewer registers and less LDS, so more
+ * workgroups per CU); the stream orders the phases, so no tile ever waits on
+ * another launch's tiles.  Both give bit-identical results. */
 typedef enum vg_exec_mode { VG_EXEC_PERSISTENT = 0, VG_EXEC_PHASED = 1 } vg_exec_mode;
 
 /* Input cloud, structure of arrays, device memory.  x, y, z: n binary32 each.
@@ -172,6 +174,31 @@ vg_status vg_downsample_batched(vg_batch_plan *plan, const vg_points *p,
                                 const int64_t *frame_offsets, const float *leaf, int B,
                                 vg_cells *out, int64_t *out_offsets, int32_t *frame_status,
                                 void *stream);
+
+/* Kernels of the pipeline, as reported by vg_batch_plan_kernel_times. */
+typedef enum vg_kernel_kind {
+  VG_KERNEL_INIT = 0,     /* state reset */
+  VG_KERNEL_BBOX = 1,     /* validity, bounding box, point records */
+  VG_KERNEL_HIST = 2,     /* cell keys and all radix-digit histograms */
+  VG_KERNEL_SORT = 3,     /* one radix pass (pass 0 also computes the keys) */
+  VG_KERNEL_REDUCE = 4,   /* segment heads, segmented sums, finalize, compaction */
+  VG_KERNEL_FIXUP = 5,    /* cells that span several reduce tiles */
+  VG_KERNEL_PIPELINE = 6  /* every phase in one persistent launch */
+} vg_kernel_kind;
+
+/* Per-launch timing.  With enable != 0 every later vg_downsample_batched call
+ * on this plan launches its kernels directly (not through the plan's graph)
+ * and records a HIP event pair on the call's stream around each launch.
+ * Waits for the plan's outstanding work before switching. */
+vg_status vg_batch_plan_set_timing(vg_batch_plan *plan, int enable);
+
+/* Durations of the kernel launches of the plan's last call, in launch order:
+ * kinds[i] (a vg_kernel_kind) and ms[i] (milliseconds between the events
+ * recorded right before and right after launch i).  Waits for the last event.
+ * At most cap entries are written (host arrays); *count receives how many.
+ * VG_ERR_ARG if timing is off. */
+vg_status vg_batch_plan_kernel_times(vg_batch_plan *plan, int *kinds, float *ms, int cap,
+                                     int *count);
 
 /* Releases the plan (waits for its work to finish first). */
 vg_status vg_batch_plan_destroy(vg_batch_plan *plan);

@@ -320,15 +320,62 @@ bool fill_staging(char* st, const Layout& L, const Variant& v, const vg_points* 
 
 // Enqueues: staged copy, state reset, pipeline.  All launches have fixed
 // shapes (no per-call kernel arguments), so the sequence can be captured.
+// Optional per-launch timing: an event pair around every kernel launch.
+struct LaunchTimer {
+  static constexpr int kMax = 32;
+  hipEvent_t ev[2 * kMax] = {};
+  int kind[kMax] = {};
+  int n = 0;
+  bool ok = false;
+  bool init() {
+    for (int i = 0; i < 2 * kMax; ++i)
+      if (hipEventCreate(&ev[i]) != hipSuccess) return false;
+    ok = true;
+    return true;
+  }
+  void release() {
+    for (int i = 0; i < 2 * kMax; ++i)
+      if (ev[i]) (void)hipEventDestroy(ev[i]);
+  }
+};
+
+vg_kernel_kind kind_of_phase(const Variant& v, int lo, int hi) {
+  if (hi - lo > 1) return VG_KERNEL_PIPELINE;
+  if (lo == 0) return VG_KERNEL_BBOX;
+  if (lo == 1) return VG_KERNEL_HIST;
+  if (lo == v.ph_red) return VG_KERNEL_REDUCE;
+  if (lo == v.ph_red + 1) return VG_KERNEL_FIXUP;
+  return VG_KERNEL_SORT;
+}
+
+// Enqueues: staged copy, state reset, pipeline.  All launches have fixed
+// shapes (no per-call kernel arguments), so the sequence can be captured.
 vg_status enqueue(const Variant& v, const Layout& L, const Ws& ws, const char* staging,
-                  int exec_mode, int cus, int bpc, hipStream_t s) {
+                  int exec_mode, int cus, int bpc, hipStream_t s, LaunchTimer* tm = nullptr) {
   if (hipMemcpyAsync(ws.hdr, staging, L.staged, hipMemcpyHostToDevice, s) != hipSuccess)
     return VG_ERR_DEVICE;
+  if (tm) tm->n = 0;
+  auto mark = [&](int k, int which) {
+    if (tm && tm->n < LaunchTimer::kMax) {
+      tm->kind[tm->n] = k;
+      (void)hipEventRecord(tm->ev[2 * tm->n + which], s);
+      if (which) ++tm->n;
+    }
+  };
+  mark(VG_KERNEL_INIT, 0);
   hipLaunchKernelGGL(vg_init_kernel, dim3(256), dim3(256), 0, s, ws);
+  mark(VG_KERNEL_INIT, 1);
   if (exec_mode == VG_EXEC_PERSISTENT) {
+    mark(VG_KERNEL_PIPELINE, 0);
     v.launch(ws, 0, v.nph, cus, bpc, s);
+    mark(VG_KERNEL_PIPELINE, 1);
   } else {
-    for (int ph = 0; ph < v.nph; ++ph) v.launch(ws, ph, ph + 1, cus, bpc, s);
+    for (int ph = 0; ph < v.nph; ++ph) {
+      const int k = kind_of_phase(v, ph, ph + 1);
+      mark(k, 0);
+      v.launch(ws, ph, ph + 1, cus, bpc, s);
+      mark(k, 1);
+    }
   }
   if (hipGetLastError() != hipSuccess) return VG_ERR_DEVICE;
   return VG_OK;
@@ -507,6 +554,7 @@ struct vg_batch_plan {
   int use_graph;
   hipGraph_t graph;
   hipGraphExec_t gexec;
+  LaunchTimer* timer;  // non-null while timing is on
 };
 
 extern "C" {
@@ -536,6 +584,7 @@ vg_status vg_batch_plan_create(int max_frames, int64_t max_total_points, vg_key_
   P->graph = nullptr;
   P->gexec = nullptr;
   P->done = nullptr;
+  P->timer = nullptr;
   vg_status rc = VG_OK;
   if (hipGetDevice(&P->device) != hipSuccess) rc = VG_ERR_DEVICE;
   if (rc == VG_OK && (P->cus = device_cus(P->device)) <= 0) rc = VG_ERR_DEVICE;
@@ -564,6 +613,50 @@ vg_status vg_batch_plan_set_graph(vg_batch_plan* plan, int use_graph) {
   return VG_OK;
 }
 
+vg_status vg_batch_plan_set_timing(vg_batch_plan* plan, int enable) {
+  if (!plan) return VG_ERR_ARG;
+  if (plan->pending) {
+    if (hipEventSynchronize(plan->done) != hipSuccess) return VG_ERR_DEVICE;
+    plan->pending = false;
+  }
+  if (!enable) {
+    if (plan->timer) {
+      plan->timer->release();
+      delete plan->timer;
+      plan->timer = nullptr;
+    }
+    return VG_OK;
+  }
+  if (plan->timer) return VG_OK;
+  LaunchTimer* t = new (std::nothrow) LaunchTimer();
+  if (!t) return VG_ERR_DEVICE;
+  if (!t->init()) {
+    t->release();
+    delete t;
+    return VG_ERR_DEVICE;
+  }
+  plan->timer = t;
+  return VG_OK;
+}
+
+vg_status vg_batch_plan_kernel_times(vg_batch_plan* plan, int* kinds, float* ms, int cap,
+                                     int* count) {
+  if (!plan || !count || cap < 0 || (cap > 0 && (!kinds || !ms))) return VG_ERR_ARG;
+  *count = 0;
+  if (!plan->timer) return VG_ERR_ARG;
+  LaunchTimer* t = plan->timer;
+  if (t->n > 0 && hipEventSynchronize(t->ev[2 * t->n - 1]) != hipSuccess) return VG_ERR_DEVICE;
+  const int n = std::min(t->n, cap);
+  for (int i = 0; i < n; ++i) {
+    float v = 0.f;
+    if (hipEventElapsedTime(&v, t->ev[2 * i], t->ev[2 * i + 1]) != hipSuccess) return VG_ERR_DEVICE;
+    kinds[i] = t->kind[i];
+    ms[i] = v;
+  }
+  *count = n;
+  return VG_OK;
+}
+
 vg_status vg_downsample_batched(vg_batch_plan* P, const vg_points* p, const int64_t* offs,
                                 const float* leaf, int B, vg_cells* out, int64_t* out_offsets,
                                 int32_t* frame_status, void* stream) {
@@ -587,7 +680,7 @@ vg_status vg_downsample_batched(vg_batch_plan* P, const vg_points* p, const int6
                     frame_status, P->key_mode, &hdr))
     return VG_ERR_ARG;
   vg_status rc = VG_OK;
-  if (P->use_graph) {
+  if (P->use_graph && !P->timer) {
     if (!P->gexec) {
       hipStream_t cs;
       if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return VG_ERR_DEVICE;
@@ -611,7 +704,7 @@ vg_status vg_downsample_batched(vg_batch_plan* P, const vg_points* p, const int6
     if (hipGraphLaunch(P->gexec, s) != hipSuccess) rc = VG_ERR_DEVICE;
   } else {
     rc = enqueue(*P->v, P->L, P->ws, P->staging, P->tuning.exec_mode, P->cus,
-                 P->tuning.blocks_per_cu, s);
+                 P->tuning.blocks_per_cu, s, P->timer);
   }
   if (hipEventRecord(P->done, s) == hipSuccess) P->pending = true;
   return rc;
@@ -623,6 +716,10 @@ vg_status vg_batch_plan_destroy(vg_batch_plan* P) {
   if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
   if (P->graph) (void)hipGraphDestroy(P->graph);
   if (P->done) (void)hipEventDestroy(P->done);
+  if (P->timer) {
+    P->timer->release();
+    delete P->timer;
+  }
   if (P->staging) (void)hipHostFree(P->staging);
   if (P->ws_base) (void)hipFree(P->ws_base);
   delete[] P->invs;

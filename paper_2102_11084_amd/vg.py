@@ -58,7 +58,11 @@ _lib_handle = None
 
 EXPORTS = ["vg_status_string", "vg_default_tuning", "vg_tuning_supported", "vg_workspace_bytes",
            "vg_downsample", "vg_downsample_ex", "vg_downsample_backward", "vg_batch_plan_create",
-           "vg_batch_plan_set_graph", "vg_downsample_batched", "vg_batch_plan_destroy"]
+           "vg_batch_plan_set_graph", "vg_downsample_batched", "vg_batch_plan_set_timing",
+           "vg_batch_plan_kernel_times", "vg_batch_plan_destroy"]
+
+# vg_kernel_kind
+KERNEL_KINDS = ("init", "bbox", "hist", "sort", "reduce", "fixup", "pipeline")
 
 
 def lib():
@@ -84,6 +88,8 @@ def lib():
         L.vg_batch_plan_set_graph.argtypes = [P, ctypes.c_int]
         L.vg_downsample_batched.argtypes = [P, ctypes.POINTER(vg_points), P, P, ctypes.c_int,
                                             ctypes.POINTER(vg_cells), P, P, P]
+        L.vg_batch_plan_set_timing.argtypes = [P, ctypes.c_int]
+        L.vg_batch_plan_kernel_times.argtypes = [P, P, P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         L.vg_batch_plan_destroy.argtypes = [P]
         for name in EXPORTS:
             if name != "vg_status_string" and name != "vg_workspace_bytes":
@@ -255,6 +261,25 @@ class BatchPlan:
         st = lib().vg_batch_plan_set_graph(self._h, 1 if use_graph else 0)
         if st != VG_OK:
             raise VGError(st, "vg_batch_plan_set_graph")
+
+    def set_timing(self, enable: bool):
+        """Per-launch HIP event timing of later runs (launches bypass the graph)."""
+        st = lib().vg_batch_plan_set_timing(self._h, 1 if enable else 0)
+        if st != VG_OK:
+            raise VGError(st, "vg_batch_plan_set_timing")
+
+    def kernel_times(self):
+        """[(kind name, ms)] of the last run's kernel launches, in launch order (waits)."""
+        cap = 64
+        kinds = (ctypes.c_int * cap)()
+        ms = (ctypes.c_float * cap)()
+        cnt = ctypes.c_int(0)
+        st = lib().vg_batch_plan_kernel_times(self._h, ctypes.cast(kinds, ctypes.c_void_p),
+                                              ctypes.cast(ms, ctypes.c_void_p), cap,
+                                              ctypes.byref(cnt))
+        if st != VG_OK:
+            raise VGError(st, "vg_batch_plan_kernel_times")
+        return [(KERNEL_KINDS[kinds[i]], float(ms[i])) for i in range(cnt.value)]
 
     def alloc_outputs(self, n_total, B, dev, outputs=ALL_OUTPUTS, have_rgb=True):
         o, cells = _alloc_cells(max(n_total, 1), n_total, dev, outputs, have_rgb)
