@@ -101,7 +101,6 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* wsum, 
 // Decoupled look-back: sum the published values of tiles k0, k0-1, ... down
 // to the first inclusive prefix.  LB descriptors are read per round trip.
 constexpr int kLookBatchSort = 4;   // per digit, per round trip
-constexpr int kLookBatchRow = 16;   // row-count chain, per round trip
 
 __device__ __forceinline__ uint32_t look_back32(const uint32_t* desc, size_t stride, int k0,
                                                 int lo, Ctl* ctl) {
@@ -140,40 +139,45 @@ __device__ __forceinline__ uint32_t look_back32(const uint32_t* desc, size_t str
   }
 }
 
-__device__ __forceinline__ uint64_t look_back64(const uint64_t* desc, int k0, Ctl* ctl) {
-  constexpr int LB = kLookBatchRow;
+// The same chain read by a whole wave: lane i reads descriptor k - i, so one
+// round trip covers 64 predecessors.  The values of the lanes up to the
+// nearest inclusive prefix are summed if every lane before it has published;
+// otherwise the published run before the first unpublished lane is summed and
+// the wave reads on from there.  Every lane returns the prefix.
+__device__ __forceinline__ uint64_t look_back64_wave(const uint64_t* desc, int k0, Ctl* ctl) {
+  const int lane = threadIdx.x & 63;
   uint64_t excl = 0;
   int k = k0;
   uint32_t spins = 0;
   for (;;) {
-    uint64_t v[LB];
+    const int idx = k - lane;
+    const uint64_t v = idx >= 0 ? ld_rlx64(desc + idx) : kFlagP64;  // before tile 0: prefix 0
+    const uint64_t fl = v & (3ull << 62);
+    const uint64_t unready = __ballot(fl == 0);
+    const int first_un = unready ? __ffsll((unsigned long long)unready) - 1 : 64;
+    const uint64_t below = first_un == 64 ? ~0ull : ((1ull << first_un) - 1ull);
+    const uint64_t pre = __ballot(fl == kFlagP64) & below;
+    const int last = pre ? __ffsll((unsigned long long)pre) - 1 : first_un - 1;
+    uint64_t part = lane <= last ? (v & kVal64) : 0ull;
 #pragma unroll
-    for (int i = 0; i < LB; ++i) v[i] = (k - i >= 0) ? ld_rlx64(desc + (k - i)) : kFlagP64;
-    int used = 0;
-    bool done = false;
-    for (int i = 0; i < LB; ++i) {
-      if (done || used < i) break;
-      const uint64_t fl = v[i] & (3ull << 62);
-      if (fl == 0) break;
-      excl += v[i] & kVal64;
-      ++used;
-      if (fl == kFlagP64) done = true;
+    for (int off = 32; off > 0; off >>= 1) {
+      const uint32_t lo = __shfl_xor((uint32_t)part, off);
+      const uint32_t hi = __shfl_xor((uint32_t)(part >> 32), off);
+      part += ((uint64_t)hi << 32) | lo;
     }
-    if (done) return excl;
-    k -= used;
-    if (k < 0) {
-      atomicOr(&ctl->error, 1u);
-      return excl;
-    }
-    if (used == 0) {
+    excl += part;
+    if (pre) return excl;
+    k -= first_un;
+    if (first_un == 0) {
       if (++spins > kSpinLimit || ((spins & 255u) == 0u && ld_rlx(&ctl->error))) {
-        atomicOr(&ctl->error, 1u);
+        if (lane == 0) atomicOr(&ctl->error, 1u);
         return excl;
       }
       __builtin_amdgcn_s_sleep(1);
     }
   }
 }
+
 
 // ------------------------------------------------------- frame params ----
 struct FrameParams {
@@ -571,6 +575,7 @@ __device__ void hist_tile(const Ws& ws, const Io& io, typename C::HistSmem& hs, 
   const int P = f.passes;
   const int Rb = 1 << f.w;
   const uint32_t mask = (uint32_t)Rb - 1u;
+  const int lane = threadIdx.x & 63;
   const int64_t t0 = (int64_t)j * C::TB;
   const int64_t cnt = min((int64_t)C::TB, fd.n - t0);
   if (f.status == kFrameOverflow) {
@@ -598,10 +603,27 @@ __device__ void hist_tile(const Ws& ws, const Io& io, typename C::HistSmem& hs, 
         if (bi + 1 < nbat) load_batch<C>(io, nxt, fd.off + t0 + c + C::BLOCK * C::UB, last, false);
 #pragma unroll
         for (int u = 0; u < C::UB; ++u) {
-          if (c + u * C::BLOCK + (int)threadIdx.x < cnt && finite3(cur.x[u], cur.y[u], cur.z[u])) {
+          // neighbouring lanes hold neighbouring points, which mostly share
+          // digits: every run of equal digits over consecutive valid lanes adds
+          // its length once (from its first lane) instead of once per point
+          const bool valid = c + u * C::BLOCK + (int)threadIdx.x < cnt &&
+                             finite3(cur.x[u], cur.y[u], cur.z[u]);
+          uint32_t lo = 0u, hi = 0u;
+          if (valid) {
             const uint64_t k = key_of_point(f, key_mode, cur.x[u], cur.y[u], cur.z[u]);
-            const uint32_t lo = (uint32_t)k, hi = (uint32_t)(k >> 32);
-            for (int p = 0; p < P; ++p) atomicAdd(&hs.h[p][digit_of(lo, hi, p * f.w, mask)], 1u);
+            lo = (uint32_t)k;
+            hi = (uint32_t)(k >> 32);
+          }
+          const uint64_t vb = __ballot(valid);
+          for (int p = 0; p < P; ++p) {
+            const uint32_t d = digit_of(lo, hi, p * f.w, mask);
+            const uint32_t dp = (uint32_t)__shfl_up((int)d, 1);
+            const bool prev_same = lane > 0 && ((vb >> (lane - 1)) & 1ull) && dp == d;
+            const bool head = valid && !prev_same;
+            const uint64_t brk = __ballot(head) | ~vb;  // a run ends before a head or an invalid lane
+            const uint64_t after = lane == 63 ? 0ull : brk & (~0ull << (lane + 1));
+            const int end = after ? __ffsll((unsigned long long)after) - 1 : 64;
+            if (head) atomicAdd(&hs.h[p][d], (uint32_t)(end - lane));
           }
         }
         cur = nxt;
@@ -644,14 +666,9 @@ __device__ void sort_tile(const Ws& ws, const Io& io, typename C::SortSmem& S, c
     return;
   }
 
-  // frame-wide digit offsets of this pass
-  {
-    uint32_t hv = 0;
-    if ((int)threadIdx.x < Rb) hv = ws.hist[((size_t)b * ws.slots + p) * C::R + threadIdx.x];
-    uint32_t tot;
-    const uint32_t ex = block_excl_scan<C::BLOCK>(hv, S.wsum, tot);
-    if ((int)threadIdx.x < C::R) S.dstart[threadIdx.x] = ex;
-  }
+  // this pass's digit counts of the frame (scanned once the items are loaded)
+  uint32_t hv = 0;
+  if ((int)threadIdx.x < Rb) hv = ws.hist[((size_t)b * ws.slots + p) * C::R + threadIdx.x];
   for (int i = threadIdx.x; i < C::NW * C::R; i += C::BLOCK) (&S.wcnt[0][0])[i] = 0u;
 
   // items in wave-striped order: wave w owns 64*SI consecutive positions
@@ -697,6 +714,12 @@ __device__ void sort_tile(const Ws& ws, const Io& io, typename C::SortSmem& S, c
 #pragma unroll
     for (int it = 0; it < C::SI; ++it)
       if (wbase + it * 64 < (int64_t)f.n_valid) vm |= 1u << it;
+  }
+  // frame-wide digit offsets of this pass
+  {
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<C::BLOCK>(hv, S.wsum, tot);
+    if ((int)threadIdx.x < C::R) S.dstart[threadIdx.x] = ex;
   }
   __syncthreads();
 
@@ -1023,20 +1046,20 @@ __device__ void red_tile(const Ws& ws, const Io& io, typename C::RedSmem& S, con
   const uint32_t Nm1 = (uint32_t)(N - 1);
   if (cnt == 0) {
     // past the frame's valid points: only the row count chain goes on
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 64) {
       uint64_t excl = 0;
-      if (t == 0) {
-        st_rlx64(&ws.rdesc[0], kFlagP64);
-      } else {
-        st_rlx64(&ws.rdesc[t], kFlagA64);
-        excl = look_back64(ws.rdesc, t - 1, ws.ctl);
+      if (t > 0) {
+        if (threadIdx.x == 0) st_rlx64(&ws.rdesc[t], kFlagA64);
+        excl = look_back64_wave(ws.rdesc, t - 1, ws.ctl);
+      }
+      if (threadIdx.x == 0) {
         st_rlx64(&ws.rdesc[t], kFlagP64 | excl);
+        if (j == 0) {
+          io.out_offsets[b] = (int64_t)excl;
+          io.frame_status[b] = ld_rlx(&ws.ctl->error) ? 5 : f.status;
+        }
+        if (t == NTr - 1) io.out_offsets[B] = (int64_t)excl;
       }
-      if (j == 0) {
-        io.out_offsets[b] = (int64_t)excl;
-        io.frame_status[b] = ld_rlx(&ws.ctl->error) ? 5 : f.status;
-      }
-      if (t == NTr - 1) io.out_offsets[B] = (int64_t)excl;
     }
     return;
   }
@@ -1105,32 +1128,17 @@ __device__ void red_tile(const Ws& ws, const Io& io, typename C::RedSmem& S, con
       if ((hmask >> i) & 1u) S.hpos[r++] = (uint16_t)(base + i);
   }
 
-  // ---- global look-back over head counts: dense rows across frames
-  if (threadIdx.x == 0) {
-    uint64_t excl = 0;
-    if (t == 0) {
-      st_rlx64(&ws.rdesc[0], kFlagP64 | H);
-    } else {
-      st_rlx64(&ws.rdesc[t], kFlagA64 | H);
-      excl = look_back64(ws.rdesc, t - 1, ws.ctl);
-      st_rlx64(&ws.rdesc[t], kFlagP64 | (excl + H));
-    }
-    S.excl = excl;
-    if (j == 0) {
-      io.out_offsets[b] = (int64_t)excl;
-      io.frame_status[b] = ld_rlx(&ws.ctl->error) ? 5 : f.status;
-    }
-    if (t == NTr - 1) io.out_offsets[B] = (int64_t)(excl + H);
-  }
-  __syncthreads();
-  const int64_t excl_t = (int64_t)S.excl;
+  // ---- publish the tile's head count at once; the look-back for the rows
+  // before it waits until the sums are done, so earlier tiles have had time
+  // to publish their prefixes
+  if (threadIdx.x == 0) st_rlx64(&ws.rdesc[t], (t == 0 ? kFlagP64 : kFlagA64) | H);
 
-  // ---- per-item values, thread-sequential segmented sums
+  // ---- per-item values: the thread's open ends (sums before its first head,
+  // and from its last head on)
   Acc pre, cur;
   acc_zero(pre);
   acc_zero(cur);
   bool seen_head = false;
-  uint32_t lh = 0;
 #pragma unroll
   for (int i = 0; i < K; ++i) {
     if (!((vmask >> i) & 1u)) continue;
@@ -1142,16 +1150,10 @@ __device__ void red_tile(const Ws& ws, const Io& io, typename C::RedSmem& S, con
       if (!seen_head) {
         pre = cur;
         seen_head = true;
-      } else {
-        // a cell that opened and closed inside this thread
-        finalize_row(io, want, excl_t + hb + lh - 1, N, cur, nullptr,
-                     cell_at<C>(S, f, key_mode, S.hpos[hb + lh - 1]));
       }
       acc_zero(cur);
-      ++lh;
     }
     acc_add(cur, dv, c24[i]);
-    if (want & kOutPointCell) io.point_cell[S.kid[base + i]] = (int32_t)(excl_t + hb + lh - 1);
   }
   if (!seen_head) pre = cur;
 
@@ -1177,6 +1179,50 @@ __device__ void red_tile(const Ws& ws, const Io& io, typename C::RedSmem& S, con
     acc_zero(ex.a);
   }
   ex = seg_combine(wp, ex);
+
+  // ---- look-back over head counts: dense rows across frames
+  if (threadIdx.x < 64) {
+    uint64_t excl = 0;
+    if (t > 0) excl = look_back64_wave(ws.rdesc, t - 1, ws.ctl);
+    if (threadIdx.x == 0) {
+      if (t > 0) st_rlx64(&ws.rdesc[t], kFlagP64 | (excl + H));
+      S.excl = excl;
+      if (j == 0) {
+        io.out_offsets[b] = (int64_t)excl;
+        io.frame_status[b] = ld_rlx(&ws.ctl->error) ? 5 : f.status;
+      }
+      if (t == NTr - 1) io.out_offsets[B] = (int64_t)(excl + H);
+    }
+  }
+  __syncthreads();
+  const int64_t excl_t = (int64_t)S.excl;
+
+  // ---- cells that open and close inside this thread, and the rows of its points
+  if (__popc(hmask) > 1 || (want & kOutPointCell)) {
+    Acc c2;
+    acc_zero(c2);
+    uint32_t lh = 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      if (!((vmask >> i) & 1u)) continue;
+      if ((hmask >> i) & 1u) {
+        if (lh > 0)
+          finalize_row(io, want, excl_t + hb + lh - 1, N, c2, nullptr,
+                       cell_at<C>(S, f, key_mode, S.hpos[hb + lh - 1]));
+        acc_zero(c2);
+        ++lh;
+      }
+      if (lh > 0 && ((hmask >> (i + 1)) & (vmask >> (i + 1))) != 0u) {
+        // a later head of this thread closes the cell: it needs the sums
+        const float p[3] = {px[i], py[i], pz[i]};
+        float r[3], dv[3];
+        corner_of(f, p, r);
+        for (int a = 0; a < 3; ++a) dv[a] = __fsub_rn(p[a], r[a]);
+        acc_add(c2, dv, c24[i]);
+      }
+      if (want & kOutPointCell) io.point_cell[S.kid[base + i]] = (int32_t)(excl_t + hb + lh - 1);
+    }
+  }
 
   // (i) the cell open at this thread's start closes at its first head
   if (seen_head) {
@@ -1366,13 +1412,23 @@ __device__ __forceinline__ void next_item(const Ws& ws, const CallHdr& hdr, Bloc
 // kind only is compiled with that kind's register and LDS needs.
 enum Kind : int { kAll = 0, kBbox = 1, kHist = 2, kSort = 3, kRed = 4, kFix = 5 };
 
+// Waves per SIMD a kernel must fit: a 512-thread radix or reduce workgroup is
+// 2 waves per SIMD, so two of them per CU need 128 VGPRs or fewer.
 template <class C, int KIND>
-__global__ __launch_bounds__(C::BLOCK) void vg_pipeline_kernel(Ws ws, int ph_lo, int ph_hi) {
+constexpr int kMinWaves = ((KIND == 3 || KIND == 4) && C::BLOCK == 512) ? 4 : 1;
+
+template <class C, int KIND>
+__global__ __launch_bounds__(C::BLOCK, (kMinWaves<C, KIND>)) void vg_pipeline_kernel(Ws ws, int ph_lo, int ph_hi) {
   __shared__ typename SmemOf<C, KIND>::type sm;
   __shared__ BlockCtl bc;
   const CallHdr hdr = *ws.hdr;
   const Io io = *ws.io;
   const bool persistent = (ph_lo == 0 && ph_hi == C::NPH);
+  // a one-pass launch of a radix pass that no frame needs ends at once (the
+  // histogram launch before it has set max_passes)
+  if (!persistent && ph_lo >= C::PH_SORT0 && ph_lo < C::PH_RED &&
+      (uint32_t)(ph_lo - C::PH_SORT0) >= ld_rlx(&ws.ctl->max_passes))
+    return;
   uint32_t* counter = persistent ? &ws.ctl->queue[0] : &ws.ctl->queue[1 + ph_lo];
   uint32_t total;
   const uint32_t nfix = (uint32_t)((hdr.NTr + C::NW - 1) / C::NW);
