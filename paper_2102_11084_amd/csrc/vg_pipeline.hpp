@@ -583,6 +583,25 @@ __device__ void hist_tile(const Ws& ws, const Io& io, typename C::HistSmem& hs, 
       for (int i = threadIdx.x; i < cnt; i += C::BLOCK) io.point_cell[fd.off + t0 + i] = -1;
     }
   } else if (P > 0) {
+    // the tile's points are requested first (all of them when they fit one
+    // batch of HB per thread), the clearing below runs while they arrive
+    constexpr int PT = C::TB / C::BLOCK;  // points per thread in a big tile
+    constexpr int HB = PT <= 16 ? PT : (PT % 16 == 0 ? 16 : (PT % 12 == 0 ? 12 : 8));
+    static_assert(C::TB % (C::BLOCK * HB) == 0, "big tile = whole histogram batches");
+    const int nbat = cnt > 0 ? (int)((cnt + C::BLOCK * HB - 1) / (C::BLOCK * HB)) : 0;
+    const int64_t last = fd.off + fd.n - 1;
+    float xs[HB], ys[HB], zs[HB];
+    auto load = [&](int bi) {
+#pragma unroll
+      for (int u = 0; u < HB; ++u) {
+        const int64_t g = min(fd.off + t0 + (int64_t)bi * C::BLOCK * HB + u * C::BLOCK +
+                                  (int)threadIdx.x, last);
+        xs[u] = io.x[g];
+        ys[u] = io.y[g];
+        zs[u] = io.z[g];
+      }
+    };
+    if (nbat > 0) load(0);
     // the look-back descriptors of the sort tiles under this big tile start cleared
     const int s_lo = j * C::KB, s_hi = min((j + 1) * C::KB, fd.nts);
     for (int p = 0; p < P; ++p) {
@@ -593,40 +612,32 @@ __device__ void hist_tile(const Ws& ws, const Io& io, typename C::HistSmem& hs, 
     }
     for (int i = threadIdx.x; i < C::MAXP * C::R; i += C::BLOCK) (&hs.h[0][0])[i] = 0u;
     __syncthreads();
-    if (cnt > 0) {
-      const int64_t last = fd.off + fd.n - 1;
-      const int nbat = (int)((cnt + C::BLOCK * C::UB - 1) / (C::BLOCK * C::UB));
-      PtBatch<C> cur, nxt;
-      load_batch<C>(io, cur, fd.off + t0, last, false);
-      for (int bi = 0; bi < nbat; ++bi) {
-        const int c = bi * C::BLOCK * C::UB;
-        if (bi + 1 < nbat) load_batch<C>(io, nxt, fd.off + t0 + c + C::BLOCK * C::UB, last, false);
+    for (int bi = 0; bi < nbat; ++bi) {
+      if (bi > 0) load(bi);
+      const int c = bi * C::BLOCK * HB;
 #pragma unroll
-        for (int u = 0; u < C::UB; ++u) {
-          // neighbouring lanes hold neighbouring points, which mostly share
-          // digits: every run of equal digits over consecutive valid lanes adds
-          // its length once (from its first lane) instead of once per point
-          const bool valid = c + u * C::BLOCK + (int)threadIdx.x < cnt &&
-                             finite3(cur.x[u], cur.y[u], cur.z[u]);
-          uint32_t lo = 0u, hi = 0u;
-          if (valid) {
-            const uint64_t k = key_of_point(f, key_mode, cur.x[u], cur.y[u], cur.z[u]);
-            lo = (uint32_t)k;
-            hi = (uint32_t)(k >> 32);
-          }
-          const uint64_t vb = __ballot(valid);
-          for (int p = 0; p < P; ++p) {
-            const uint32_t d = digit_of(lo, hi, p * f.w, mask);
-            const uint32_t dp = (uint32_t)__shfl_up((int)d, 1);
-            const bool prev_same = lane > 0 && ((vb >> (lane - 1)) & 1ull) && dp == d;
-            const bool head = valid && !prev_same;
-            const uint64_t brk = __ballot(head) | ~vb;  // a run ends before a head or an invalid lane
-            const uint64_t after = lane == 63 ? 0ull : brk & (~0ull << (lane + 1));
-            const int end = after ? __ffsll((unsigned long long)after) - 1 : 64;
-            if (head) atomicAdd(&hs.h[p][d], (uint32_t)(end - lane));
-          }
+      for (int u = 0; u < HB; ++u) {
+        // neighbouring lanes hold neighbouring points, which mostly fall in
+        // one cell: every run of equal keys over consecutive valid lanes adds
+        // its length to each pass's digit once, from its first lane
+        const bool valid = c + u * C::BLOCK + (int)threadIdx.x < cnt && finite3(xs[u], ys[u], zs[u]);
+        uint32_t lo = 0u, hi = 0u;
+        if (valid) {
+          const uint64_t k = key_of_point(f, key_mode, xs[u], ys[u], zs[u]);
+          lo = (uint32_t)k;
+          hi = (uint32_t)(k >> 32);
         }
-        cur = nxt;
+        const uint64_t vb = __ballot(valid);
+        const uint32_t plo = (uint32_t)__shfl_up((int)lo, 1);
+        const uint32_t phi = f.wide ? (uint32_t)__shfl_up((int)hi, 1) : 0u;
+        const bool prev_same = lane > 0 && ((vb >> (lane - 1)) & 1ull) && plo == lo && phi == hi;
+        const bool head = valid && !prev_same;
+        const uint64_t brk = __ballot(head) | ~vb;  // a run ends before a head or an invalid lane
+        if (head) {
+          const uint64_t after = lane == 63 ? 0ull : brk & (~0ull << (lane + 1));
+          const uint32_t len = (uint32_t)((after ? __ffsll((unsigned long long)after) - 1 : 64) - lane);
+          for (int p = 0; p < P; ++p) atomicAdd(&hs.h[p][digit_of(lo, hi, p * f.w, mask)], len);
+        }
       }
     }
     __syncthreads();
