@@ -353,7 +353,6 @@ struct Cfg {
   static constexpr int TS = BLOCK * SI;      // sort tile
   static constexpr int KB = 2;
   static constexpr int TB = TS * KB;         // big tile (bbox, histogram)
-  static constexpr int UB = 4;               // points per thread per load batch of a big tile
   static constexpr int W = RADIX_;
   static constexpr int R = 1 << W;
   static constexpr int MAXP = (63 + W - 1) / W;
@@ -364,7 +363,6 @@ struct Cfg {
   static_assert(R <= BLOCK, "one digit per thread in the look-back");
   static_assert(MAXP <= kMaxPassSlots, "pass slots");
   static_assert(SI <= 32 && RI <= 32, "item masks are 32-bit");
-  static_assert(TB % (BLOCK * UB) == 0, "big tile = whole load batches");
   static_assert(TR <= 8192, "reduce tile: 16-bit item positions, 21-bit colour sums");
 
   struct SortSmem {
@@ -405,6 +403,9 @@ struct Cfg {
 
 // LDS of a kernel entry: every phase's layout for the persistent kernel,
 // only its own phase's for a one-phase kernel.
+// Phase kinds a kernel can hold (see vg_pipeline_kernel).
+enum Kind : int { kAll = 0, kBbox = 1, kHist = 2, kSort = 3, kRed = 4, kFix = 5 };
+
 template <class C, int KIND>
 struct SmemOf {
   union type {
@@ -460,100 +461,187 @@ struct SmemOf<C, 5> {
   union type { typename C::BboxSmem bbox; };
 };
 
-// Points of a big tile are streamed in batches of UB per thread; the next
-// batch is in flight while the current one is processed.
-template <class C>
-struct PtBatch {
-  float x[C::UB], y[C::UB], z[C::UB];
-  uint32_t c[C::UB];
+// The call's input and output pointers reach the kernels through memory, so
+// the compiler cannot tell that they point to global memory and would access
+// them with flat instructions, which every LDS wait then also waits for.  The
+// kernels use them through this view, whose pointers are global ones.
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+
+struct GIo {
+  gptr<const float> x, y, z;
+  gptr<const uint8_t> rgb;
+  gptr<float> cx, cy, cz;
+  gptr<uint8_t> crgb;
+  gptr<uint32_t> count;
+  gptr<uint64_t> key;
+  gptr<int32_t> point_cell;
+  gptr<uint32_t> ref_index;
+  gptr<float> lx, ly, lz;
+  gptr<int64_t> out_offsets;
+  gptr<int32_t> frame_status;
 };
 
-template <class C>
-__device__ __forceinline__ void load_batch(const Io& io, PtBatch<C>& pb, int64_t g0, int64_t last,
-                                           bool with_rgb) {
+__device__ __forceinline__ GIo global_view(const Io& o) {
+  GIo g;
+  g.x = (gptr<const float>)o.x;
+  g.y = (gptr<const float>)o.y;
+  g.z = (gptr<const float>)o.z;
+  g.rgb = (gptr<const uint8_t>)o.rgb;
+  g.cx = (gptr<float>)o.cx;
+  g.cy = (gptr<float>)o.cy;
+  g.cz = (gptr<float>)o.cz;
+  g.crgb = (gptr<uint8_t>)o.crgb;
+  g.count = (gptr<uint32_t>)o.count;
+  g.key = (gptr<uint64_t>)o.key;
+  g.point_cell = (gptr<int32_t>)o.point_cell;
+  g.ref_index = (gptr<uint32_t>)o.ref_index;
+  g.lx = (gptr<float>)o.lx;
+  g.ly = (gptr<float>)o.ly;
+  g.lz = (gptr<float>)o.lz;
+  g.out_offsets = (gptr<int64_t>)o.out_offsets;
+  g.frame_status = (gptr<int32_t>)o.frame_status;
+  return g;
+}
+
+// Points of a big tile (bbox and histogram tiles) are read in batches of HB
+// per thread, lane-consecutive: point i of a batch goes to lane i mod BLOCK.
+template <int HB>
+struct Pts {
+  float x[HB], y[HB], z[HB];
+  uint32_t c[HB];  // packed rgb (bbox tiles only)
+};
+
+template <class C, int HB, bool RGB = true>
+__device__ __forceinline__ void load_pts(const GIo& io, Pts<HB>& p, int64_t g0, int64_t last,
+                                         bool with_rgb) {
 #pragma unroll
-  for (int u = 0; u < C::UB; ++u) {
+  for (int u = 0; u < HB; ++u) {
     const int64_t g = min(g0 + u * C::BLOCK + (int)threadIdx.x, last);
-    pb.x[u] = io.x[g];
-    pb.y[u] = io.y[g];
-    pb.z[u] = io.z[g];
-    pb.c[u] = 0u;
-    if (with_rgb) {
-      const uint8_t* q = io.rgb + 3 * (size_t)g;
-      pb.c[u] = (uint32_t)q[0] | ((uint32_t)q[1] << 8) | ((uint32_t)q[2] << 16);
+    p.x[u] = io.x[g];
+    p.y[u] = io.y[g];
+    p.z[u] = io.z[g];
+    p.c[u] = 0u;
+    if (RGB && with_rgb) {
+      const gptr<const uint8_t> q = io.rgb + 3 * (size_t)g;
+      p.c[u] = (uint32_t)q[0] | ((uint32_t)q[1] << 8) | ((uint32_t)q[2] << 16);
     }
   }
 }
 
-// ---------------------------------------------------------- BBOX tile ----
-template <class C>
-__device__ void bbox_tile(const Ws& ws, const Io& io, typename C::BboxSmem& bs, const FrameDesc& fd,
-                          int b, int j, uint32_t want, bool persistent) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t t0 = (int64_t)j * C::TB;
-  const int64_t cnt = min((int64_t)C::TB, fd.n - t0);
-  uint32_t mn[3] = {0u, 0u, 0u}, mx[3] = {0u, 0u, 0u}, nv = 0;
-  if (cnt > 0) {
-    const int64_t last = fd.off + fd.n - 1;
-    const int nbat = (int)((cnt + C::BLOCK * C::UB - 1) / (C::BLOCK * C::UB));
-    const bool with_rgb = io.rgb != nullptr;
-    PtBatch<C> cur, nxt;
-    load_batch<C>(io, cur, fd.off + t0, last, with_rgb);
-    for (int bi = 0; bi < nbat; ++bi) {
-      const int c = bi * C::BLOCK * C::UB;
-      if (bi + 1 < nbat) load_batch<C>(io, nxt, fd.off + t0 + c + C::BLOCK * C::UB, last, with_rgb);
+// Points per thread of one batch: 4 in tiles taken from the work queue (the
+// persistent kernel holds every phase's registers); in one-phase launches,
+// which stream with the next batch in flight, 4 for bbox tiles (which also
+// carry colours and write records) and 8 for histogram tiles.
+constexpr int kBigBatch = 4;
+template <int KIND>
+constexpr int kStreamBatch = KIND == kBbox ? 4 : 8;
+
+// A value every lane of the wave holds alike (read from LDS at a uniform
+// address), moved to scalar registers.
+template <class T>
+__device__ __forceinline__ T wave_uniform(const T& v) {
+  static_assert(sizeof(T) % 4 == 0, "whole dwords");
+  uint32_t w[sizeof(T) / 4];
+  __builtin_memcpy(w, &v, sizeof(T));
 #pragma unroll
-      for (int u = 0; u < C::UB; ++u) {
-        const int64_t i = c + u * C::BLOCK + (int)threadIdx.x;
-        if (i < cnt) {
-          const int64_t g = fd.off + t0 + i;
-          ws.rec[g] = make_float4(cur.x[u], cur.y[u], cur.z[u], __uint_as_float(cur.c[u]));
-          if (finite3(cur.x[u], cur.y[u], cur.z[u])) {
-            const uint32_t ex = f2ord(cur.x[u]), ey = f2ord(cur.y[u]), ez = f2ord(cur.z[u]);
-            mn[0] = max(mn[0], ~ex); mn[1] = max(mn[1], ~ey); mn[2] = max(mn[2], ~ez);
-            mx[0] = max(mx[0], ex); mx[1] = max(mx[1], ey); mx[2] = max(mx[2], ez);
-            nv += 1;
-          } else if (want & kOutPointCell) {
-            io.point_cell[g] = -1;
-          }
-        }
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+  T r;
+  __builtin_memcpy(&r, w, sizeof(T));
+  return r;
+}
+
+// ---------------------------------------------------------- BBOX tile ----
+struct BboxAcc {
+  uint32_t mn[3], mx[3], nv;  // order-preserving encodings: max of ~enc (min) and of enc (max)
+};
+
+__device__ __forceinline__ void bbox_zero(BboxAcc& a) {
+  for (int q = 0; q < 3; ++q) a.mn[q] = a.mx[q] = 0u;
+  a.nv = 0u;
+}
+
+// One batch: the 16 B record of every point, the valid points' box and count,
+// row -1 for invalid points.  `g0` is the batch's first point, `rem` the points
+// of the tile from there on.
+template <class C, int HB>
+__device__ __forceinline__ void bbox_batch(const Ws& ws, const GIo& io, BboxAcc& a,
+                                           const Pts<HB>& p, int64_t g0, int64_t rem,
+                                           uint32_t want) {
+#pragma unroll
+  for (int u = 0; u < HB; ++u) {
+    const int64_t i = u * C::BLOCK + (int)threadIdx.x;
+    if (i < rem) {
+      const int64_t g = g0 + i;
+      ws.rec[g] = make_float4(p.x[u], p.y[u], p.z[u], __uint_as_float(p.c[u]));
+      if (finite3(p.x[u], p.y[u], p.z[u])) {
+        const uint32_t ex = f2ord(p.x[u]), ey = f2ord(p.y[u]), ez = f2ord(p.z[u]);
+        a.mn[0] = max(a.mn[0], ~ex); a.mn[1] = max(a.mn[1], ~ey); a.mn[2] = max(a.mn[2], ~ez);
+        a.mx[0] = max(a.mx[0], ex); a.mx[1] = max(a.mx[1], ey); a.mx[2] = max(a.mx[2], ez);
+        a.nv += 1;
+      } else if (want & kOutPointCell) {
+        io.point_cell[g] = -1;
       }
-      cur = nxt;
     }
   }
+}
+
+// End of a bbox tile: block reduction, frame atomics, done counter.
+template <class C>
+__device__ __forceinline__ void bbox_finish(const Ws& ws, typename C::BboxSmem& bs, BboxAcc& a,
+                                            int b, bool persistent) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
-    for (int a = 0; a < 3; ++a) {
-      mn[a] = max(mn[a], (uint32_t)__shfl_xor(mn[a], off));
-      mx[a] = max(mx[a], (uint32_t)__shfl_xor(mx[a], off));
+    for (int q = 0; q < 3; ++q) {
+      a.mn[q] = max(a.mn[q], (uint32_t)__shfl_xor(a.mn[q], off));
+      a.mx[q] = max(a.mx[q], (uint32_t)__shfl_xor(a.mx[q], off));
     }
-    nv += __shfl_xor(nv, off);
+    a.nv += __shfl_xor(a.nv, off);
   }
   if (lane == 0) {
-    for (int a = 0; a < 3; ++a) { bs.mn[w][a] = mn[a]; bs.mx[w][a] = mx[a]; }
-    bs.nv[w] = nv;
+    for (int q = 0; q < 3; ++q) { bs.mn[w][q] = a.mn[q]; bs.mx[w][q] = a.mx[q]; }
+    bs.nv[w] = a.nv;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t tn = 0;
     for (int i = 0; i < C::NW; ++i) {
       tn += bs.nv[i];
-      for (int a = 0; a < 3; ++a) {
-        mn[a] = max(mn[a], bs.mn[i][a]);
-        mx[a] = max(mx[a], bs.mx[i][a]);
+      for (int q = 0; q < 3; ++q) {
+        a.mn[q] = max(a.mn[q], bs.mn[i][q]);
+        a.mx[q] = max(a.mx[q], bs.mx[i][q]);
       }
     }
     FrameState* fs = ws.fs + b;
     if (tn) {
-      for (int a = 0; a < 3; ++a) {
-        atomicMax(&fs->mn_neg[a], mn[a]);
-        atomicMax(&fs->mx[a], mx[a]);
+      for (int q = 0; q < 3; ++q) {
+        atomicMax(&fs->mn_neg[q], a.mn[q]);
+        atomicMax(&fs->mx[q], a.mx[q]);
       }
       atomicAdd(&fs->n_valid, tn);
     }
     if (persistent) fence_rel();
     atomicAdd(&fs->bbox_done, 1u);
   }
+  __syncthreads();  // bs is reused by the next tile
+}
+
+template <class C>
+__device__ void bbox_tile(const Ws& ws, const GIo& io, typename C::BboxSmem& bs, const FrameDesc& fd,
+                          int b, int j, uint32_t want, bool persistent) {
+  constexpr int HB = kBigBatch;
+  static_assert(C::TB % (C::BLOCK * HB) == 0, "big tile = whole load batches");
+  const int64_t t0 = (int64_t)j * C::TB;
+  const int64_t cnt = min((int64_t)C::TB, fd.n - t0);
+  BboxAcc a;
+  bbox_zero(a);
+  for (int64_t c = 0; c < cnt; c += C::BLOCK * HB) {
+    Pts<HB> p;
+    load_pts<C, HB>(io, p, fd.off + t0 + c, fd.off + fd.n - 1, io.rgb != nullptr);
+    bbox_batch<C, HB>(ws, io, a, p, fd.off + t0 + c, cnt - c, want);
+  }
+  bbox_finish<C>(ws, bs, a, b, persistent);
 }
 
 __device__ __forceinline__ uint32_t digit_of(uint32_t lo, uint32_t hi, int shift, uint32_t mask) {
@@ -568,83 +656,79 @@ __device__ __forceinline__ uint64_t key_of_point(const FrameParams& f, int key_m
 }
 
 // ---------------------------------------------------------- HIST tile ----
+// Start of a histogram tile: the look-back descriptors of the radix tiles
+// under it start cleared.
 template <class C>
-__device__ void hist_tile(const Ws& ws, const Io& io, typename C::HistSmem& hs, const FrameDesc& fd,
-                          int b, int j, const FrameParams& f, int key_mode, uint32_t want,
-                          bool persistent) {
-  const int P = f.passes;
-  const int Rb = 1 << f.w;
-  const uint32_t mask = (uint32_t)Rb - 1u;
+__device__ __forceinline__ void hist_start(const Ws& ws, const FrameDesc& fd, int j,
+                                           const FrameParams& f) {
+  if (f.status == kFrameOverflow) return;
+  const int s_lo = j * C::KB, s_hi = min((j + 1) * C::KB, fd.nts);
+  for (int p = 0; p < f.passes; ++p) {
+    for (int st = s_lo; st < s_hi; ++st) {
+      uint32_t* row = ws.sdesc + ((size_t)p * ws.capNTs + fd.ts0 + st) * C::R;
+      for (int d = threadIdx.x; d < C::R; d += C::BLOCK) row[d] = 0u;
+    }
+  }
+}
+
+// One batch: every pass's digit counted in the LDS histogram.  Neighbouring
+// lanes hold neighbouring points, which mostly fall in one cell: every run of
+// equal keys over consecutive valid lanes adds its length to each pass's digit
+// once, from its first lane.  An overflowing frame's points get row -1.
+template <class C, int HB>
+__device__ __forceinline__ void hist_batch(const GIo& io, typename C::HistSmem& hs,
+                                           const FrameParams& f, int key_mode, const Pts<HB>& p,
+                                           int64_t g0, int64_t rem, uint32_t want) {
   const int lane = threadIdx.x & 63;
-  const int64_t t0 = (int64_t)j * C::TB;
-  const int64_t cnt = min((int64_t)C::TB, fd.n - t0);
   if (f.status == kFrameOverflow) {
-    if ((want & kOutPointCell) && cnt > 0) {
-      for (int i = threadIdx.x; i < cnt; i += C::BLOCK) io.point_cell[fd.off + t0 + i] = -1;
-    }
-  } else if (P > 0) {
-    // the tile's points are requested first (all of them when they fit one
-    // batch of HB per thread), the clearing below runs while they arrive
-    constexpr int PT = C::TB / C::BLOCK;  // points per thread in a big tile
-    constexpr int HB = PT <= 16 ? PT : (PT % 16 == 0 ? 16 : (PT % 12 == 0 ? 12 : 8));
-    static_assert(C::TB % (C::BLOCK * HB) == 0, "big tile = whole histogram batches");
-    const int nbat = cnt > 0 ? (int)((cnt + C::BLOCK * HB - 1) / (C::BLOCK * HB)) : 0;
-    const int64_t last = fd.off + fd.n - 1;
-    float xs[HB], ys[HB], zs[HB];
-    auto load = [&](int bi) {
+    if (want & kOutPointCell) {
 #pragma unroll
       for (int u = 0; u < HB; ++u) {
-        const int64_t g = min(fd.off + t0 + (int64_t)bi * C::BLOCK * HB + u * C::BLOCK +
-                                  (int)threadIdx.x, last);
-        xs[u] = io.x[g];
-        ys[u] = io.y[g];
-        zs[u] = io.z[g];
-      }
-    };
-    if (nbat > 0) load(0);
-    // the look-back descriptors of the sort tiles under this big tile start cleared
-    const int s_lo = j * C::KB, s_hi = min((j + 1) * C::KB, fd.nts);
-    for (int p = 0; p < P; ++p) {
-      for (int st = s_lo; st < s_hi; ++st) {
-        uint32_t* row = ws.sdesc + ((size_t)p * ws.capNTs + fd.ts0 + st) * C::R;
-        for (int d = threadIdx.x; d < C::R; d += C::BLOCK) row[d] = 0u;
+        const int64_t i = u * C::BLOCK + (int)threadIdx.x;
+        if (i < rem) io.point_cell[g0 + i] = -1;
       }
     }
-    for (int i = threadIdx.x; i < C::MAXP * C::R; i += C::BLOCK) (&hs.h[0][0])[i] = 0u;
-    __syncthreads();
-    for (int bi = 0; bi < nbat; ++bi) {
-      if (bi > 0) load(bi);
-      const int c = bi * C::BLOCK * HB;
+    return;
+  }
+  const int P = f.passes;
+  if (P == 0) return;
+  const uint32_t mask = (1u << f.w) - 1u;
 #pragma unroll
-      for (int u = 0; u < HB; ++u) {
-        // neighbouring lanes hold neighbouring points, which mostly fall in
-        // one cell: every run of equal keys over consecutive valid lanes adds
-        // its length to each pass's digit once, from its first lane
-        const bool valid = c + u * C::BLOCK + (int)threadIdx.x < cnt && finite3(xs[u], ys[u], zs[u]);
-        uint32_t lo = 0u, hi = 0u;
-        if (valid) {
-          const uint64_t k = key_of_point(f, key_mode, xs[u], ys[u], zs[u]);
-          lo = (uint32_t)k;
-          hi = (uint32_t)(k >> 32);
-        }
-        const uint64_t vb = __ballot(valid);
-        const uint32_t plo = (uint32_t)__shfl_up((int)lo, 1);
-        const uint32_t phi = f.wide ? (uint32_t)__shfl_up((int)hi, 1) : 0u;
-        const bool prev_same = lane > 0 && ((vb >> (lane - 1)) & 1ull) && plo == lo && phi == hi;
-        const bool head = valid && !prev_same;
-        const uint64_t brk = __ballot(head) | ~vb;  // a run ends before a head or an invalid lane
-        if (head) {
-          const uint64_t after = lane == 63 ? 0ull : brk & (~0ull << (lane + 1));
-          const uint32_t len = (uint32_t)((after ? __ffsll((unsigned long long)after) - 1 : 64) - lane);
-          for (int p = 0; p < P; ++p) atomicAdd(&hs.h[p][digit_of(lo, hi, p * f.w, mask)], len);
-        }
-      }
+  for (int u = 0; u < HB; ++u) {
+    const bool valid = u * C::BLOCK + (int)threadIdx.x < rem && finite3(p.x[u], p.y[u], p.z[u]);
+    uint32_t lo = 0u, hi = 0u;
+    if (valid) {
+      const uint64_t k = key_of_point(f, key_mode, p.x[u], p.y[u], p.z[u]);
+      lo = (uint32_t)k;
+      hi = (uint32_t)(k >> 32);
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < P * C::R; i += C::BLOCK) {
-      const int p = i / C::R, d = i % C::R;
-      const uint32_t v = hs.h[p][d];
-      if (v) atomicAdd(&ws.hist[((size_t)b * ws.slots + p) * C::R + d], v);
+    const uint64_t vb = __ballot(valid);
+    const uint32_t plo = (uint32_t)__shfl_up((int)lo, 1);
+    const uint32_t phi = f.wide ? (uint32_t)__shfl_up((int)hi, 1) : 0u;
+    const bool prev_same = lane > 0 && ((vb >> (lane - 1)) & 1ull) && plo == lo && phi == hi;
+    const bool head = valid && !prev_same;
+    const uint64_t brk = __ballot(head) | ~vb;  // a run ends before a head or an invalid lane
+    if (head) {
+      const uint64_t after = lane == 63 ? 0ull : brk & (~0ull << (lane + 1));
+      const uint32_t len = (uint32_t)((after ? __ffsll((unsigned long long)after) - 1 : 64) - lane);
+      for (int q = 0; q < P; ++q) atomicAdd(&hs.h[q][digit_of(lo, hi, q * f.w, mask)], len);
+    }
+  }
+}
+
+// End of a histogram tile: the LDS counts go to the frame's histograms (and
+// are cleared for the next tile), then the done counters.
+template <class C>
+__device__ __forceinline__ void hist_finish(const Ws& ws, typename C::HistSmem& hs, int b,
+                                            const FrameParams& f, bool persistent) {
+  const int P = f.status == kFrameOverflow ? 0 : f.passes;
+  __syncthreads();
+  for (int i = threadIdx.x; i < P * C::R; i += C::BLOCK) {
+    const int q = i / C::R, d = i % C::R;
+    const uint32_t v = hs.h[q][d];
+    if (v) {
+      atomicAdd(&ws.hist[((size_t)b * ws.slots + q) * C::R + d], v);
+      hs.h[q][d] = 0u;
     }
   }
   __syncthreads();
@@ -656,9 +740,120 @@ __device__ void hist_tile(const Ws& ws, const Io& io, typename C::HistSmem& hs, 
   }
 }
 
+template <class C>
+__device__ void hist_tile(const Ws& ws, const GIo& io, typename C::HistSmem& hs, const FrameDesc& fd,
+                          int b, int j, const FrameParams& f, int key_mode, uint32_t want,
+                          bool persistent) {
+  constexpr int HB = kBigBatch;
+  static_assert(C::TB % (C::BLOCK * HB) == 0, "big tile = whole load batches");
+  const int64_t t0 = (int64_t)j * C::TB;
+  const int64_t cnt = min((int64_t)C::TB, fd.n - t0);
+  // the LDS histogram shares its memory with other phases' tiles
+  for (int i = threadIdx.x; i < C::MAXP * C::R; i += C::BLOCK) (&hs.h[0][0])[i] = 0u;
+  hist_start<C>(ws, fd, j, f);
+  __syncthreads();
+  for (int64_t c = 0; c < cnt; c += C::BLOCK * HB) {
+    Pts<HB> p;
+    load_pts<C, HB>(io, p, fd.off + t0 + c, fd.off + fd.n - 1, false);
+    hist_batch<C, HB>(io, hs, f, key_mode, p, fd.off + t0 + c, cnt - c, want);
+  }
+  hist_finish<C>(ws, hs, b, f, persistent);
+}
+
+// Big tiles of a one-phase bbox or histogram launch (frames cached in LDS,
+// at least one point in the call).  These tiles wait on nothing, so tile t
+// goes to workgroup t mod G without a queue, and each workgroup streams its
+// tiles' points: the next batch (of this tile or of the workgroup's next tile)
+// is requested before the current one is processed.  That request is made on
+// every iteration (of point 0 when there is no next batch), so the number of
+// loads in flight is the same on every path and the wait for the current
+// batch does not drain the next one.
+template <class C, int KIND, bool RGB>
+__device__ void stream_big_tiles(const Ws& ws, const GIo& io, const CallHdr& hdr, BlockCtl& bc,
+                                 typename SmemOf<C, KIND>::type& sm) {
+  constexpr int HB = kStreamBatch<KIND>;
+  constexpr int64_t BS = (int64_t)C::BLOCK * HB;
+  static_assert(C::TB % (C::BLOCK * HB) == 0, "big tile = whole load batches");
+  const int G = gridDim.x, NT = hdr.NTb;
+  if constexpr (KIND == kHist) {
+    for (int i = threadIdx.x; i < C::MAXP * C::R; i += C::BLOCK) (&sm.hist.h[0][0])[i] = 0u;
+  }
+  // tile t -> frame b (largest b with tp[b] <= t), tile j in it
+  auto frame_of = [&](int t) {
+    int lo = 0, hi = hdr.B;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if ((int)bc.tp[0][mid] <= t) lo = mid;
+      else hi = mid;
+    }
+    return __builtin_amdgcn_readfirstlane(lo);
+  };
+  int t = blockIdx.x;
+  if (t >= NT) return;
+  int b = frame_of(t);
+  int64_t t0 = (int64_t)(t - (int)__builtin_amdgcn_readfirstlane(bc.tp[0][b])) * C::TB;
+  int64_t off = wave_uniform(bc.fda[b].off), fn = wave_uniform(bc.fda[b].n);
+  int64_t cnt = min((int64_t)C::TB, fn - t0);
+  int64_t c = 0;  // batch start within the tile
+  Pts<HB> cur, nxt;
+  if (cnt > 0) load_pts<C, HB, RGB>(io, cur, off + t0, off + fn - 1, true);
+  else load_pts<C, HB, RGB>(io, cur, 0, 0, true);
+  BboxAcc acc;
+  bbox_zero(acc);
+  FrameParams f;
+  if constexpr (KIND == kHist) {
+    f = wave_uniform(bc.fpa[b]);
+    hist_start<C>(ws, bc.fda[b], (int)(t0 / C::TB), f);
+  }
+  __syncthreads();
+  for (;;) {
+    // the batch after this one
+    int t2 = t, b2 = b;
+    int64_t t02 = t0, off2 = off, fn2 = fn, cnt2 = cnt, c2 = c + BS;
+    if (c2 >= cnt) {
+      t2 = t + G;
+      c2 = 0;
+      if (t2 < NT) {
+        b2 = frame_of(t2);
+        t02 = (int64_t)(t2 - (int)__builtin_amdgcn_readfirstlane(bc.tp[0][b2])) * C::TB;
+        off2 = wave_uniform(bc.fda[b2].off);
+        fn2 = wave_uniform(bc.fda[b2].n);
+        cnt2 = min((int64_t)C::TB, fn2 - t02);
+      }
+    }
+    const bool more = t2 < NT && cnt2 > 0;
+    load_pts<C, HB, RGB>(io, nxt, more ? off2 + t02 + c2 : 0, more ? off2 + fn2 - 1 : 0, true);
+    if (cnt > 0) {
+      if constexpr (KIND == kBbox) bbox_batch<C, HB>(ws, io, acc, cur, off + t0 + c, cnt - c, hdr.want);
+      else hist_batch<C, HB>(io, sm.hist, f, hdr.key_mode, cur, off + t0 + c, cnt - c, hdr.want);
+    }
+    if (t2 != t) {
+      if constexpr (KIND == kBbox) {
+        bbox_finish<C>(ws, sm.bbox, acc, b, false);
+        bbox_zero(acc);
+      } else {
+        hist_finish<C>(ws, sm.hist, b, f, false);
+        if (t2 < NT) {
+          f = wave_uniform(bc.fpa[b2]);
+          hist_start<C>(ws, bc.fda[b2], (int)(t02 / C::TB), f);
+        }
+      }
+      if (t2 >= NT) break;
+    }
+    cur = nxt;
+    t = t2;
+    b = b2;
+    t0 = t02;
+    off = off2;
+    fn = fn2;
+    cnt = cnt2;
+    c = c2;
+  }
+}
+
 // ---------------------------------------------------------- SORT tile ----
 template <class C>
-__device__ void sort_tile(const Ws& ws, const Io& io, typename C::SortSmem& S, const FrameDesc& fd,
+__device__ void sort_tile(const Ws& ws, const GIo& io, typename C::SortSmem& S, const FrameDesc& fd,
                           int b, int j, int p, const FrameParams& f, int key_mode,
                           bool persistent) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -859,7 +1054,7 @@ __device__ __forceinline__ void corner_of_key(const FrameParams& f, int key_mode
 }
 
 // Writes one output row from a segment's sums.
-__device__ __forceinline__ void finalize_row(const Io& io, uint32_t want, int64_t row, int64_t N,
+__device__ __forceinline__ void finalize_row(const GIo& io, uint32_t want, int64_t row, int64_t N,
                                              const Acc& a, const uint64_t* rgb_wide,
                                              const CellOut& c) {
   if (row < 0 || row >= N || a.n == 0 || c.ref >= N) return;
@@ -911,7 +1106,7 @@ __device__ __forceinline__ void write_pend(const Ws& ws, int t, int b, int j, co
 // Fix-up of one reduce tile by one wave: a cell that began in an earlier tile
 // gets the carry-out parts of the tiles it covers, summed in a fixed order.
 template <class C>
-__device__ void fix_tile(const Ws& ws, const Io& io, int t, int key_mode, uint32_t want,
+__device__ void fix_tile(const Ws& ws, const GIo& io, int t, int key_mode, uint32_t want,
                          int64_t N) {
   const int lane = threadIdx.x & 63;
   const Pend pd = ws.pend[t];
@@ -1039,7 +1234,7 @@ __device__ __forceinline__ CellOut cell_at(const typename C::RedSmem& S, const F
 }
 
 template <class C>
-__device__ void red_tile(const Ws& ws, const Io& io, typename C::RedSmem& S, const FrameDesc& fd,
+__device__ void red_tile(const Ws& ws, const GIo& io, typename C::RedSmem& S, const FrameDesc& fd,
                          int b, int j, const FrameParams& f, int key_mode, uint32_t want, int B,
                          int NTr, int64_t N, bool persistent) {
   constexpr int K = C::RI;
@@ -1421,7 +1616,6 @@ __device__ __forceinline__ void next_item(const Ws& ws, const CallHdr& hdr, Bloc
 // (one persistent launch over the whole queue) or one phase kind (one launch
 // per phase).  Every kind runs the same tile code; a kernel that holds one
 // kind only is compiled with that kind's register and LDS needs.
-enum Kind : int { kAll = 0, kBbox = 1, kHist = 2, kSort = 3, kRed = 4, kFix = 5 };
 
 // Waves per SIMD a kernel must fit: a 512-thread radix or reduce workgroup is
 // 2 waves per SIMD, so two of them per CU need 128 VGPRs or fewer.
@@ -1433,7 +1627,7 @@ __global__ __launch_bounds__(C::BLOCK, (kMinWaves<C, KIND>)) void vg_pipeline_ke
   __shared__ typename SmemOf<C, KIND>::type sm;
   __shared__ BlockCtl bc;
   const CallHdr hdr = *ws.hdr;
-  const Io io = *ws.io;
+  const GIo io = global_view(*ws.io);
   const bool persistent = (ph_lo == 0 && ph_hi == C::NPH);
   // a one-pass launch of a radix pass that no frame needs ends at once (the
   // histogram launch before it has set max_passes)
@@ -1459,12 +1653,14 @@ __global__ __launch_bounds__(C::BLOCK, (kMinWaves<C, KIND>)) void vg_pipeline_ke
     for (int i = threadIdx.x; i <= hdr.ilv_rounds; i += C::BLOCK) bc.ilv_s[i] = ws.ilv_s[i];
     for (int i = threadIdx.x; i < hdr.B; i += C::BLOCK) bc.ilv_perm[i] = ws.ilv_perm[i];
   }
-  // a one-phase launch after the bbox pass: every frame's grid is final
-  const bool cache = !persistent && ph_lo != C::PH_BBOX && hdr.B <= kFpCache;
-  if (cache) {
+  // a one-phase launch keeps the frame descriptors in LDS, and after the bbox
+  // pass every frame's grid too (it is final by then)
+  const bool cache_fd = !persistent && hdr.B <= kFpCache;
+  const bool cache = cache_fd && ph_lo != C::PH_BBOX;
+  if (cache_fd) {
     for (int i = threadIdx.x; i < hdr.B; i += C::BLOCK) {
       bc.fda[i] = ws.fd[i];
-      bc.fpa[i] = frame_params(ws, i, hdr.key_mode, C::W);
+      if (cache) bc.fpa[i] = frame_params(ws, i, hdr.key_mode, C::W);
     }
   }
   if (threadIdx.x == 0) {
@@ -1529,6 +1725,13 @@ __global__ __launch_bounds__(C::BLOCK, (kMinWaves<C, KIND>)) void vg_pipeline_ke
   __syncthreads();
   if (own_order) total = bc.ilv_total;
   if (bc.item >= total && total > 0) return;
+  if constexpr (KIND == kBbox || KIND == kHist) {
+    if (cache_fd && hdr.N > 0) {
+      if (KIND == kBbox && io.rgb != nullptr) stream_big_tiles<C, KIND, true>(ws, io, hdr, bc, sm);
+      else stream_big_tiles<C, KIND, false>(ws, io, hdr, bc, sm);
+      return;
+    }
+  }
   for (;;) {
     if (threadIdx.x == 0) next_item<C>(ws, hdr, bc, counter, persistent, ph_lo, total);
     __syncthreads();
