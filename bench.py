@@ -33,11 +33,12 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def frame_passes(x, y, z, leaf, radix_bits):
-    """Radix passes of a frame under the library's rule (host-side accounting only)."""
+def frame_passes(x, y, z, leaf, radix_bits, with_bits=False):
+    """Radix passes (and key bits) of a frame under the library's rule
+    (host-side byte accounting only)."""
     v = np.isfinite(x) & np.isfinite(y) & np.isfinite(z)
     if not v.any():
-        return 0
+        return (0, 0) if with_bits else 0
     inv = np.float32(1.0) / np.float32(leaf)
     dims = []
     for a in (x, y, z):
@@ -46,7 +47,8 @@ def frame_passes(x, y, z, leaf, radix_bits):
         dims.append(int(np.floor(t)) + 1)
     top = dims[0] * dims[1] * dims[2] - 1
     bits = top.bit_length()
-    return max(1, math.ceil(bits / radix_bits))
+    passes = max(1, math.ceil(bits / radix_bits))
+    return (passes, bits) if with_bits else passes
 
 
 def algorithmic_bytes(n, nv, passes, m, point_cell=False):
@@ -58,21 +60,27 @@ def algorithmic_bytes(n, nv, passes, m, point_cell=False):
     return 24 * n + (8 + 4 + 16 * passes + 8 + 15 + (4 if point_cell else 0)) * nv + 27 * m
 
 
-def kernel_bytes(n, nv, passes, m, point_cell=False):
+def kernel_bytes(n, nv, passes, m, narrow, point_cell=False):
     """Algorithmic bytes per step of each kernel of the phased pipeline, summed
     over frames (lists indexed like the frames):
       bbox    reads xyz of every point                      12 B x n
       hist    reads xyz of every point to form the keys      12 B x n
-      sort    pass 0 reads xyz, writes (key, index) pairs    12 B x n + 8 B x n_v
+              and stores them when they fit 31 bits          +4 B x n
+      sort    pass 0 reads the stored keys (else xyz) and    4 B (12 B) x n
+              writes (key, index) pairs                      + 8 B x n_v
               pass p > 0 reads and writes the pairs          16 B x n_v of frames with > p passes
       reduce  reads the pairs, gathers xyz + rgb             23 B x n_v (+4 B x n_v point rows)
               writes xyz, rgb, count, key per cell           27 B x m
     """
     n, nv, passes, m = (np.asarray(a, dtype=np.int64) for a in (n, nv, passes, m))
+    narrow = np.asarray(narrow, dtype=bool)
     live = passes > 0
-    sort = int((12 * n).sum() + (8 * nv[live]).sum() + (16 * nv * np.maximum(passes - 1, 0)).sum())
+    key_in = np.where(narrow & live, 4, 12)
+    sort = int((key_in * n).sum() + (8 * nv[live]).sum() +
+               (16 * nv * np.maximum(passes - 1, 0)).sum())
     red = int(((23 + (4 if point_cell else 0)) * nv).sum() + (27 * m).sum())
-    b = {"init": 0, "bbox": int(12 * n.sum()), "hist": int(12 * n.sum()), "sort": sort,
+    hist = int((12 * n).sum() + (4 * n[narrow & live]).sum())
+    b = {"init": 0, "bbox": int(12 * n.sum()), "hist": hist, "sort": sort,
          "reduce": red, "fixup": 0}
     b["pipeline"] = sum(b.values())
     return b
@@ -205,8 +213,10 @@ def main():
     assert (o["frame_status"] == 0).all(), "a frame failed"
     m_frames = np.diff(o["out_offsets"])
     radix = tuning.radix_bits
-    passes = np.array([frame_passes(x[offs[b]:offs[b + 1]], y[offs[b]:offs[b + 1]],
-                                    z[offs[b]:offs[b + 1]], leaves[b], radix) for b in range(len(leaves))])
+    pb = np.array([frame_passes(x[offs[b]:offs[b + 1]], y[offs[b]:offs[b + 1]],
+                                z[offs[b]:offs[b + 1]], leaves[b], radix, with_bits=True)
+                   for b in range(len(leaves))])
+    passes, bits = pb[:, 0], pb[:, 1]
     alg = sum(algorithmic_bytes(int(offs[b + 1] - offs[b]), int(nv_frames[b]), int(passes[b]),
                                 int(m_frames[b]), args.point_cell) for b in range(len(leaves)))
     step_achieved = alg / (ev_ms * 1e-3) / 1e9
@@ -223,7 +233,7 @@ def main():
             launches[kind] = launches.get(kind, 0) + 1
     plan.set_timing(False)
     ks = max(args.kernel_steps, 1)
-    kb = kernel_bytes(np.diff(offs), nv_frames, passes, m_frames, args.point_cell)
+    kb = kernel_bytes(np.diff(offs), nv_frames, passes, m_frames, bits <= 31, args.point_cell)
     kinds = {k: {"ms_per_step": round(v / ks, 4), "launches_per_step": launches[k] // ks,
                  "avg_launch_ms": round(v / launches[k], 4),
                  "algorithmic_bytes_per_step": kb[k],

@@ -188,8 +188,12 @@ struct FrameParams {
   uint32_t n_valid;
   int bits, passes, w;
   bool wide;
+  bool narrow;  // keys fit 31 bits: the histogram pass stores them for radix pass 0
   int status;
 };
+
+// Stored key of an invalid point (never a key of a narrow frame).
+constexpr uint32_t kNoKey = 0xffffffffu;
 
 __device__ __forceinline__ uint64_t spread3(uint32_t v) {
   uint64_t x = v & 0x1fffffu;
@@ -232,6 +236,7 @@ __device__ FrameParams frame_params(const Ws& ws, int b, int key_mode, int radix
   f.passes = 0;
   f.w = 0;
   f.wide = false;
+  f.narrow = false;
   for (int a = 0; a < 3; ++a) { f.mn[a] = 0.f; f.d[a] = 0; }
   if (f.n_valid == 0) return f;
   for (int a = 0; a < 3; ++a) {
@@ -253,6 +258,7 @@ __device__ FrameParams frame_params(const Ws& ws, int b, int key_mode, int radix
   }
   f.bits = top ? 64 - __clzll(top) : 0;
   f.wide = f.bits > 32;
+  f.narrow = f.bits <= 31;
   f.passes = f.bits == 0 ? 1 : (f.bits + radix_bits - 1) / radix_bits;
   f.w = (f.bits + f.passes - 1) / f.passes;
   return f;
@@ -676,7 +682,7 @@ __device__ __forceinline__ void hist_start(const Ws& ws, const FrameDesc& fd, in
 // equal keys over consecutive valid lanes adds its length to each pass's digit
 // once, from its first lane.  An overflowing frame's points get row -1.
 template <class C, int HB>
-__device__ __forceinline__ void hist_batch(const GIo& io, typename C::HistSmem& hs,
+__device__ __forceinline__ void hist_batch(const Ws& ws, const GIo& io, typename C::HistSmem& hs,
                                            const FrameParams& f, int key_mode, const Pts<HB>& p,
                                            int64_t g0, int64_t rem, uint32_t want) {
   const int lane = threadIdx.x & 63;
@@ -702,6 +708,8 @@ __device__ __forceinline__ void hist_batch(const GIo& io, typename C::HistSmem& 
       lo = (uint32_t)k;
       hi = (uint32_t)(k >> 32);
     }
+    if (f.narrow && u * C::BLOCK + (int)threadIdx.x < rem)
+      ws.lo[0][g0 + u * C::BLOCK + (int)threadIdx.x] = valid ? lo : kNoKey;
     const uint64_t vb = __ballot(valid);
     const uint32_t plo = (uint32_t)__shfl_up((int)lo, 1);
     const uint32_t phi = f.wide ? (uint32_t)__shfl_up((int)hi, 1) : 0u;
@@ -755,7 +763,7 @@ __device__ void hist_tile(const Ws& ws, const GIo& io, typename C::HistSmem& hs,
   for (int64_t c = 0; c < cnt; c += C::BLOCK * HB) {
     Pts<HB> p;
     load_pts<C, HB>(io, p, fd.off + t0 + c, fd.off + fd.n - 1, false);
-    hist_batch<C, HB>(io, hs, f, key_mode, p, fd.off + t0 + c, cnt - c, want);
+    hist_batch<C, HB>(ws, io, hs, f, key_mode, p, fd.off + t0 + c, cnt - c, want);
   }
   hist_finish<C>(ws, hs, b, f, persistent);
 }
@@ -825,7 +833,7 @@ __device__ void stream_big_tiles(const Ws& ws, const GIo& io, const CallHdr& hdr
     load_pts<C, HB, RGB>(io, nxt, more ? off2 + t02 + c2 : 0, more ? off2 + fn2 - 1 : 0, true);
     if (cnt > 0) {
       if constexpr (KIND == kBbox) bbox_batch<C, HB>(ws, io, acc, cur, off + t0 + c, cnt - c, hdr.want);
-      else hist_batch<C, HB>(io, sm.hist, f, hdr.key_mode, cur, off + t0 + c, cnt - c, hdr.want);
+      else hist_batch<C, HB>(ws, io, sm.hist, f, hdr.key_mode, cur, off + t0 + c, cnt - c, hdr.want);
     }
     if (t2 != t) {
       if constexpr (KIND == kBbox) {
@@ -881,7 +889,19 @@ __device__ void sort_tile(const Ws& ws, const GIo& io, typename C::SortSmem& S, 
   uint32_t klo[C::SI], khi[C::SI], kid[C::SI];
   uint32_t vm = 0;
   const int64_t wbase = t0 + (int64_t)w * 64 * C::SI + lane;
-  if (p == 0) {
+  if (p == 0 && f.narrow) {
+    // keys stored by the histogram pass, in input order
+    const int64_t last = fd.off + max(fd.n - 1, (int64_t)0);
+#pragma unroll
+    for (int it = 0; it < C::SI; ++it) klo[it] = ws.lo[0][min(fd.off + wbase + it * 64, last)];
+#pragma unroll
+    for (int it = 0; it < C::SI; ++it) {
+      const int64_t pos = wbase + it * 64;
+      khi[it] = 0u;
+      kid[it] = (uint32_t)(fd.off + pos);
+      if (pos < fd.n && klo[it] != kNoKey) vm |= 1u << it;
+    }
+  } else if (p == 0) {
     const int64_t last = fd.off + max(fd.n - 1, (int64_t)0);
     float xs[C::SI], ys[C::SI], zs[C::SI];
 #pragma unroll
