@@ -71,7 +71,7 @@ const Variant kVariants[] = {
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
-const vg_tuning kDefaultTuning = {512, 8, 8, 512, 4, 0, VG_EXEC_PHASED};
+const vg_tuning kDefaultTuning = {512, 8, 8, 512, 8, 0, VG_EXEC_PHASED};
 
 const Variant* find_variant(const vg_tuning* t) {
   if (!t) t = &kDefaultTuning;
