@@ -1290,32 +1290,29 @@ __device__ void red_tile(const Ws& ws, const GIo& io, typename C::RedSmem& S, co
     return;
   }
 
-  // ---- keys and indices to LDS, gathered points to registers
-  // (blocked: thread i owns items i*K .. i*K+K-1 of the tile)
-  float px[K], py[K], pz[K];
-  uint32_t c24[K];
+  // ---- keys and indices to LDS with lane-consecutive (coalesced) loads; each
+  // thread then owns items i*K .. i*K+K-1 of the tile (blocked) and gathers
+  // their points into registers
   {
     const int64_t lastp = e0 - 1;
-    uint32_t id_[K];
 #pragma unroll
-    for (int i = 0; i < K; ++i) {
-      const int64_t pos = min(s0 + base + i, lastp);
+    for (int u = 0; u < K; ++u) {
+      const int li = u * C::BLOCK + (int)threadIdx.x;
+      const int64_t pos = min(s0 + li, lastp);
       const uint32_t lo = klo[pos];
-      const uint32_t hi = f.wide ? khi[pos] : 0u;
-      id_[i] = min(kid[pos], Nm1);
-      if (base + i < cnt) {
-        S.klo[base + i] = lo;
-        if (f.wide) S.khi[base + i] = hi;
-        S.kid[base + i] = id_[i];
+      const uint32_t id = min(kid[pos], Nm1);
+      if (li < cnt) {
+        S.klo[li] = lo;
+        S.kid[li] = id;
       }
     }
+    if (f.wide) {
 #pragma unroll
-    for (int i = 0; i < K; ++i) {
-      const float4 r4 = ws.rec[id_[i]];
-      px[i] = r4.x;
-      py[i] = r4.y;
-      pz[i] = r4.z;
-      c24[i] = __float_as_uint(r4.w);
+      for (int u = 0; u < K; ++u) {
+        const int li = u * C::BLOCK + (int)threadIdx.x;
+        const uint32_t hi = khi[min(s0 + li, lastp)];
+        if (li < cnt) S.khi[li] = hi;
+      }
     }
   }
   if (threadIdx.x == 0) {
@@ -1328,6 +1325,17 @@ __device__ void red_tile(const Ws& ws, const GIo& io, typename C::RedSmem& S, co
     S.next_hi = (e0 < nv && f.wide) ? khi[e0] : 0u;
   }
   __syncthreads();
+  float px[K], py[K], pz[K];
+  uint32_t c24[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    const uint32_t id = S.kid[min(base + i, cnt - 1)];
+    const float4 r4 = ws.rec[id];
+    px[i] = r4.x;
+    py[i] = r4.y;
+    pz[i] = r4.z;
+    c24[i] = __float_as_uint(r4.w);
+  }
 
   // ---- head flags: an item starts a cell when its key differs from the previous one
   uint32_t vmask = 0, hmask = 0;
