@@ -677,15 +677,57 @@ __device__ __forceinline__ void hist_start(const Ws& ws, const FrameDesc& fd, in
   }
 }
 
+// The key of point_key with the key mode and key width fixed at compile time.
+template <int KM, bool WIDE>
+__device__ __forceinline__ uint64_t key_fixed(const FrameParams& f, float x, float y, float z) {
+  const uint32_t kx = cell_coord(x, f.mn[0], f.inv);
+  const uint32_t ky = cell_coord(y, f.mn[1], f.inv);
+  const uint32_t kz = cell_coord(z, f.mn[2], f.inv);
+  if constexpr (KM == 1) return spread3(kx) | (spread3(ky) << 1) | (spread3(kz) << 2);
+  else if constexpr (!WIDE) return (uint64_t)(kx + f.d[0] * (ky + f.d[1] * kz));
+  else return (uint64_t)kx + (uint64_t)f.d[0] * ((uint64_t)ky + (uint64_t)f.d[1] * (uint64_t)kz);
+}
+
+template <class C, int HB, int KM, bool WIDE>
+__device__ __forceinline__ void hist_batch_fixed(const Ws& ws, typename C::HistSmem& hs,
+                                                 const FrameParams& f, const Pts<HB>& p,
+                                                 int64_t g0, int64_t rem) {
+  const int lane = threadIdx.x & 63;
+  const int P = f.passes;
+  const uint32_t mask = (1u << f.w) - 1u;
+#pragma unroll
+  for (int u = 0; u < HB; ++u) {
+    const bool inr = u * C::BLOCK + (int)threadIdx.x < rem;
+    const bool valid = inr && finite3(p.x[u], p.y[u], p.z[u]);
+    // an invalid point's key is formed from the grid minimum and dropped
+    const uint64_t k = key_fixed<KM, WIDE>(f, valid ? p.x[u] : f.mn[0], valid ? p.y[u] : f.mn[1],
+                                           valid ? p.z[u] : f.mn[2]);
+    const uint32_t lo = valid ? (uint32_t)k : 0u;
+    const uint32_t hi = WIDE && valid ? (uint32_t)(k >> 32) : 0u;
+    if (!WIDE && f.narrow && inr) ws.lo[0][g0 + u * C::BLOCK + (int)threadIdx.x] = valid ? lo : kNoKey;
+    const uint64_t vb = __ballot(valid);
+    const uint32_t plo = (uint32_t)__shfl_up((int)lo, 1);
+    const uint32_t phi = WIDE ? (uint32_t)__shfl_up((int)hi, 1) : 0u;
+    const bool prev_same = lane > 0 && ((vb >> (lane - 1)) & 1ull) && plo == lo && phi == hi;
+    const bool head = valid && !prev_same;
+    const uint64_t brk = __ballot(head) | ~vb;  // a run ends before a head or an invalid lane
+    if (head) {
+      const uint64_t after = lane == 63 ? 0ull : brk & (~0ull << (lane + 1));
+      const uint32_t len = (uint32_t)((after ? __ffsll((unsigned long long)after) - 1 : 64) - lane);
+      for (int q = 0; q < P; ++q) atomicAdd(&hs.h[q][digit_of(lo, hi, q * f.w, mask)], len);
+    }
+  }
+}
+
 // One batch: every pass's digit counted in the LDS histogram.  Neighbouring
 // lanes hold neighbouring points, which mostly fall in one cell: every run of
 // equal keys over consecutive valid lanes adds its length to each pass's digit
-// once, from its first lane.  An overflowing frame's points get row -1.
+// once, from its first lane.  Keys of frames that fit 31 bits are stored for
+// radix pass 0.  An overflowing frame's points get row -1.
 template <class C, int HB>
 __device__ __forceinline__ void hist_batch(const Ws& ws, const GIo& io, typename C::HistSmem& hs,
                                            const FrameParams& f, int key_mode, const Pts<HB>& p,
                                            int64_t g0, int64_t rem, uint32_t want) {
-  const int lane = threadIdx.x & 63;
   if (f.status == kFrameOverflow) {
     if (want & kOutPointCell) {
 #pragma unroll
@@ -696,31 +738,13 @@ __device__ __forceinline__ void hist_batch(const Ws& ws, const GIo& io, typename
     }
     return;
   }
-  const int P = f.passes;
-  if (P == 0) return;
-  const uint32_t mask = (1u << f.w) - 1u;
-#pragma unroll
-  for (int u = 0; u < HB; ++u) {
-    const bool valid = u * C::BLOCK + (int)threadIdx.x < rem && finite3(p.x[u], p.y[u], p.z[u]);
-    uint32_t lo = 0u, hi = 0u;
-    if (valid) {
-      const uint64_t k = key_of_point(f, key_mode, p.x[u], p.y[u], p.z[u]);
-      lo = (uint32_t)k;
-      hi = (uint32_t)(k >> 32);
-    }
-    if (f.narrow && u * C::BLOCK + (int)threadIdx.x < rem)
-      ws.lo[0][g0 + u * C::BLOCK + (int)threadIdx.x] = valid ? lo : kNoKey;
-    const uint64_t vb = __ballot(valid);
-    const uint32_t plo = (uint32_t)__shfl_up((int)lo, 1);
-    const uint32_t phi = f.wide ? (uint32_t)__shfl_up((int)hi, 1) : 0u;
-    const bool prev_same = lane > 0 && ((vb >> (lane - 1)) & 1ull) && plo == lo && phi == hi;
-    const bool head = valid && !prev_same;
-    const uint64_t brk = __ballot(head) | ~vb;  // a run ends before a head or an invalid lane
-    if (head) {
-      const uint64_t after = lane == 63 ? 0ull : brk & (~0ull << (lane + 1));
-      const uint32_t len = (uint32_t)((after ? __ffsll((unsigned long long)after) - 1 : 64) - lane);
-      for (int q = 0; q < P; ++q) atomicAdd(&hs.h[q][digit_of(lo, hi, q * f.w, mask)], len);
-    }
+  if (f.passes == 0) return;
+  if (key_mode == 1) {
+    if (f.wide) hist_batch_fixed<C, HB, 1, true>(ws, hs, f, p, g0, rem);
+    else hist_batch_fixed<C, HB, 1, false>(ws, hs, f, p, g0, rem);
+  } else {
+    if (f.wide) hist_batch_fixed<C, HB, 0, true>(ws, hs, f, p, g0, rem);
+    else hist_batch_fixed<C, HB, 0, false>(ws, hs, f, p, g0, rem);
   }
 }
 
