@@ -153,3 +153,38 @@ def test_full_uneven_batch_sampled():
         fr["point_cell"] = g["point_cell"][s0:s1]
         fr["m"] = hi - lo
         assert_matches_oracle(fr, r, float(leaves[b]), point_cell_offset=lo, ref_offset=s0)
+
+
+def many_frames(B, seed):
+    """B uneven clouds: sizes 0..6000, some empty, some with NaN/Inf points,
+    leaves 0.02..0.2, one wide-key frame; exercises the paths for batches
+    beyond the frames whose tables and grids fit in LDS."""
+    rng = np.random.default_rng(seed)
+    xs, ys, zs, cs, sizes, leaves = [], [], [], [], [], []
+    for b in range(B):
+        n = 0 if b % 17 == 3 else int(rng.integers(1, 6000))
+        p = rng.uniform(-1.0, 2.0, size=(n, 3)).astype(np.float32)
+        if b % 5 == 1 and n:
+            bad = rng.random(n) < 0.2
+            p[bad, rng.integers(0, 3)] = np.nan
+        if b % 29 == 7 and n > 1:  # keys over 32 bits
+            p[0] = (-500.0, -500.0, -500.0)
+            p[1] = (500.0, 500.0, 500.0)
+        xs.append(p[:, 0].copy())
+        ys.append(p[:, 1].copy())
+        zs.append(p[:, 2].copy())
+        cs.append(rng.integers(0, 256, size=(n, 3), dtype=np.uint8))
+        sizes.append(n)
+        leaves.append(0.5 if b % 29 == 7 else float(rng.choice([0.02, 0.05, 0.1, 0.2])))
+    offs = np.zeros(B + 1, np.int64)
+    offs[1:] = np.cumsum(sizes)
+    return (np.concatenate(xs), np.concatenate(ys), np.concatenate(zs), np.concatenate(cs), offs,
+            np.array(leaves, np.float32))
+
+
+@pytest.mark.parametrize("B", [100, 300])
+def test_many_frames_match_per_frame_oracle(B):
+    print(f"case batch of {B} frames", flush=True)
+    x, y, z, rgb, offs, leaves = many_frames(B, seed=B)
+    g = run_batched(x, y, z, rgb, offs, leaves)
+    check_against_oracle(g, x, y, z, rgb, offs, leaves)
