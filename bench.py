@@ -226,9 +226,12 @@ def main():
     # event pair on the plan's stream around every kernel
     plan.set_timing(True)
     per_kind, launches = {}, {}
+    per_launch = None
     for _ in range(max(args.kernel_steps, 1)):
         plan.run(*d, offs, leaves, out=outs)
-        for kind, ms in plan.kernel_times():
+        kt = plan.kernel_times()
+        per_launch = kt if per_launch is None else [(k, a + b) for (k, a), (_, b) in zip(per_launch, kt)]
+        for kind, ms in kt:
             per_kind[kind] = per_kind.get(kind, 0.0) + ms
             launches[kind] = launches.get(kind, 0) + 1
     plan.set_timing(False)
@@ -248,6 +251,8 @@ def main():
     log(f"kernels per step: " + ", ".join(f"{k} {v['ms_per_step']:.3f} ms x{v['launches_per_step']}"
                                           f" ({v['gbs']} GB/s)" for k, v in kinds.items()))
     log(f"dominant kernel: {dom}, {dom_ms:.4f} ms/launch, {achieved:.1f} GB/s; traffic: {tsrc}")
+    log("launches (ms, mean over the timing steps): " +
+        " ".join(f"{k}:{v / max(args.kernel_steps, 1):.3f}" for k, v in per_launch))
     result = {
         "metric": METRIC, "value": round(value, 2), "unit": "Mpoints/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
