@@ -1530,14 +1530,21 @@ __device__ void red_tile(const Ws& ws, const GIo& io, typename C::RedSmem& S, co
 }
 
 // ---------------------------------------------------------- pipeline ----
-// Thread 0 of a workgroup: take the next item, find its frame, wait for its
-// inputs (once per frame and phase), prepare the frame's grid parameters.
+// Thread 0 of a workgroup: take the next item (a queue ticket, or with `stat`
+// item blockIdx.x + k * gridDim.x on the k-th call), find its frame, wait for
+// its inputs (once per frame and phase), prepare the frame's grid parameters.
 template <class C>
 __device__ __forceinline__ void next_item(const Ws& ws, const CallHdr& hdr, BlockCtl& bc,
                                        uint32_t* counter, bool persistent, int ph_lo,
-                                       uint32_t total) {
+                                       uint32_t total, bool stat, uint32_t& sitem) {
   for (;;) {
-    const uint32_t item = atomicAdd(counter, 1u);
+    uint32_t item;
+    if (stat) {  // tiles that wait on no tile: a fixed order
+      item = sitem;
+      sitem += gridDim.x;
+    } else {
+      item = atomicAdd(counter, 1u);
+    }
     bc.item = item;
     bc.skip = 0;
     if (item >= total) return;
@@ -1784,8 +1791,12 @@ __global__ __launch_bounds__(C::BLOCK, (kMinWaves<C, KIND>)) void vg_pipeline_ke
       return;
     }
   }
+  // fix-up tiles only read what the reduce launch wrote: workgroup g takes
+  // items g, g + G, ... instead of queue tickets
+  const bool stat = !persistent && KIND == kFix;
+  uint32_t sitem = blockIdx.x;
   for (;;) {
-    if (threadIdx.x == 0) next_item<C>(ws, hdr, bc, counter, persistent, ph_lo, total);
+    if (threadIdx.x == 0) next_item<C>(ws, hdr, bc, counter, persistent, ph_lo, total, stat, sitem);
     __syncthreads();
     if (bc.item >= total) break;
     const int ph = bc.ph, b = bc.b, j = bc.j;
