@@ -320,6 +320,9 @@ bool fill_staging(char* st, const Layout& L, const Variant& v, const vg_points* 
 
 // Enqueues: staged copy, state reset, pipeline.  All launches have fixed
 // shapes (no per-call kernel arguments), so the sequence can be captured.
+// Radix passes launched one by one; later passes share a launch.
+constexpr int kOwnPasses = 3;
+
 // Optional per-launch timing: an event pair around every kernel launch.
 struct LaunchTimer {
   static constexpr int kMax = 32;
@@ -340,7 +343,7 @@ struct LaunchTimer {
 };
 
 vg_kernel_kind kind_of_phase(const Variant& v, int lo, int hi) {
-  if (hi - lo > 1) return VG_KERNEL_PIPELINE;
+  if (hi - lo > 1) return (lo >= 2 && hi <= v.ph_red) ? VG_KERNEL_SORT : VG_KERNEL_PIPELINE;
   if (lo == 0) return VG_KERNEL_BBOX;
   if (lo == 1) return VG_KERNEL_HIST;
   if (lo == v.ph_red) return VG_KERNEL_REDUCE;
@@ -370,11 +373,16 @@ vg_status enqueue(const Variant& v, const Layout& L, const Ws& ws, const char* s
     v.launch(ws, 0, v.nph, cus, bpc, s);
     mark(VG_KERNEL_PIPELINE, 1);
   } else {
-    for (int ph = 0; ph < v.nph; ++ph) {
-      const int k = kind_of_phase(v, ph, ph + 1);
+    // one launch per phase, except that the radix passes from kOwnPasses on
+    // (keys of more than 24 bits with 8-bit digits) share one launch, which
+    // ends at once when no frame needs them
+    for (int ph = 0; ph < v.nph;) {
+      const int hi = (ph == 2 + kOwnPasses && v.ph_red > ph + 1) ? v.ph_red : ph + 1;
+      const int k = kind_of_phase(v, ph, hi);
       mark(k, 0);
-      v.launch(ws, ph, ph + 1, cus, bpc, s);
+      v.launch(ws, ph, hi, cus, bpc, s);
       mark(k, 1);
+      ph = hi;
     }
   }
   if (hipGetLastError() != hipSuccess) return VG_ERR_DEVICE;

@@ -1533,9 +1533,11 @@ __device__ void red_tile(const Ws& ws, const GIo& io, typename C::RedSmem& S, co
 // Thread 0 of a workgroup: take the next item (a queue ticket, or with `stat`
 // item blockIdx.x + k * gridDim.x on the k-th call), find its frame, wait for
 // its inputs (once per frame and phase), prepare the frame's grid parameters.
+// A launch of several radix passes (`multi`, not `persistent`) numbers its
+// items pass after pass; a tile of pass p waits for pass p - 1 of its frame.
 template <class C>
 __device__ __forceinline__ void next_item(const Ws& ws, const CallHdr& hdr, BlockCtl& bc,
-                                       uint32_t* counter, bool persistent, int ph_lo,
+                                       uint32_t* counter, bool persistent, bool multi, int ph_lo,
                                        uint32_t total, bool stat, uint32_t& sitem) {
   for (;;) {
     uint32_t item;
@@ -1564,6 +1566,9 @@ __device__ __forceinline__ void next_item(const Ws& ws, const CallHdr& hdr, Bloc
         ph = C::PH_FIX;
         base = 2 * nb + C::MAXP * ns + (uint32_t)hdr.NTr;
       }
+    } else if (multi) {
+      ph = ph_lo + (int)(item / ns);
+      base = (uint32_t)(ph - ph_lo) * ns;
     } else {
       ph = ph_lo;
       base = 0;
@@ -1642,14 +1647,14 @@ __device__ __forceinline__ void next_item(const Ws& ws, const CallHdr& hdr, Bloc
         // (in round-robin order a frame's tiles are not contiguous: skip one)
         uint32_t jump = bc.ilv_rounds > 0 ? 0u : base + (uint32_t)(fd.ts0 + fd.nts);
         const bool all_hist = wait_geq(&ws.ctl->hist_tiles_done, (uint32_t)hdr.NTb, ws.ctl);
-        if (persistent) fence_acq();
+        if (multi) fence_acq();
         if (all_hist && (uint32_t)p >= ld_rlx(&ws.ctl->max_passes))
           jump = persistent ? 2 * nb + C::MAXP * ns : total;
         if (jump) atomicMax(counter, jump);
         continue;
       }
       if (bc.dep_b[ph] != b) {
-        if (persistent) {
+        if (multi) {
           wait_geq(&ws.fs[b].hist_done, (uint32_t)fd.ntb, ws.ctl);
           if (p > 0) wait_geq(&ws.fs[b].pass_done[p - 1], (uint32_t)fd.nts, ws.ctl);
           fence_acq();
@@ -1688,8 +1693,9 @@ __global__ __launch_bounds__(C::BLOCK, (kMinWaves<C, KIND>)) void vg_pipeline_ke
   const CallHdr hdr = *ws.hdr;
   const GIo io = global_view(*ws.io);
   const bool persistent = (ph_lo == 0 && ph_hi == C::NPH);
-  // a one-pass launch of a radix pass that no frame needs ends at once (the
-  // histogram launch before it has set max_passes)
+  const bool multi = ph_hi - ph_lo > 1;  // several phases: tiles wait on earlier phases
+  // a launch of radix passes that no frame needs ends at once (the histogram
+  // launch before it has set max_passes)
   if (!persistent && ph_lo >= C::PH_SORT0 && ph_lo < C::PH_RED &&
       (uint32_t)(ph_lo - C::PH_SORT0) >= ld_rlx(&ws.ctl->max_passes))
     return;
@@ -1700,7 +1706,7 @@ __global__ __launch_bounds__(C::BLOCK, (kMinWaves<C, KIND>)) void vg_pipeline_ke
   else if (ph_lo <= C::PH_HIST) total = (uint32_t)hdr.NTb;
   else if (ph_lo == C::PH_RED) total = (uint32_t)hdr.NTr;
   else if (ph_lo == C::PH_FIX) total = nfix;
-  else total = (uint32_t)hdr.NTs;
+  else total = (uint32_t)(ph_hi - ph_lo) * (uint32_t)hdr.NTs;
   if (hdr.B <= kLdsFrames) {
     for (int i = threadIdx.x; i <= hdr.B; i += C::BLOCK) {
       bc.tp[0][i] = ws.tpb[i];
@@ -1728,7 +1734,7 @@ __global__ __launch_bounds__(C::BLOCK, (kMinWaves<C, KIND>)) void vg_pipeline_ke
   }
   // a one-pass radix launch with every frame's grid at hand orders its tiles
   // round-robin over just the frames that need this pass
-  const bool own_order = cache && ph_lo >= C::PH_SORT0 && ph_lo < C::PH_RED &&
+  const bool own_order = cache && !multi && ph_lo >= C::PH_SORT0 && ph_lo < C::PH_RED &&
                          hdr.ilv_rounds > 0 && hdr.B <= kIlvMaxFrames;
   if (own_order) {
     // keep the host order (frames by descending sort-tile count) of just the
@@ -1796,7 +1802,8 @@ __global__ __launch_bounds__(C::BLOCK, (kMinWaves<C, KIND>)) void vg_pipeline_ke
   const bool stat = !persistent && KIND == kFix;
   uint32_t sitem = blockIdx.x;
   for (;;) {
-    if (threadIdx.x == 0) next_item<C>(ws, hdr, bc, counter, persistent, ph_lo, total, stat, sitem);
+    if (threadIdx.x == 0)
+      next_item<C>(ws, hdr, bc, counter, persistent, multi, ph_lo, total, stat, sitem);
     __syncthreads();
     if (bc.item >= total) break;
     const int ph = bc.ph, b = bc.b, j = bc.j;
@@ -1816,7 +1823,7 @@ __global__ __launch_bounds__(C::BLOCK, (kMinWaves<C, KIND>)) void vg_pipeline_ke
           hist_tile<C>(ws, io, sm.hist, fd, b, j, f, hdr.key_mode, hdr.want, persistent);
       } else if (ph < C::PH_RED) {
         if constexpr (KIND == kAll || KIND == kSort)
-          sort_tile<C>(ws, io, sm.sort, fd, b, j, ph - C::PH_SORT0, f, hdr.key_mode, persistent);
+          sort_tile<C>(ws, io, sm.sort, fd, b, j, ph - C::PH_SORT0, f, hdr.key_mode, multi);
       } else {
         if constexpr (KIND == kAll || KIND == kRed) {
           red_tile<C>(ws, io, sm.red, fd, b, j, f, hdr.key_mode, hdr.want, hdr.B, hdr.NTr, hdr.N,
