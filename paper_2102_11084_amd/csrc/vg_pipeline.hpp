@@ -1277,6 +1277,19 @@ __device__ __forceinline__ CellOut cell_at(const typename C::RedSmem& S, const F
   return c;
 }
 
+// Reduce tiles of a frame past its valid points (all but its first tile) are
+// skipped at dequeue.  The frame's last tile that is not skipped publishes
+// their inclusive prefix, which is its own, so the look-back of later tiles
+// passes through them, and writes the total rows if the frame is the last.
+template <class C>
+__device__ __forceinline__ void publish_skipped(const Ws& ws, const GIo& io, const FrameDesc& fd,
+                                                int j, int64_t nv, int b, int B, uint64_t incl) {
+  const int jl = nv > 0 ? (int)((nv - 1) / C::TR) : 0;
+  if (j != jl) return;
+  for (int k = jl + 1; k < fd.ntr; ++k) st_rlx64(&ws.rdesc[fd.tr0 + k], kFlagP64 | incl);
+  if (b == B - 1) io.out_offsets[B] = (int64_t)incl;
+}
+
 template <class C>
 __device__ void red_tile(const Ws& ws, const GIo& io, typename C::RedSmem& S, const FrameDesc& fd,
                          int b, int j, const FrameParams& f, int key_mode, uint32_t want, int B,
@@ -1309,6 +1322,7 @@ __device__ void red_tile(const Ws& ws, const GIo& io, typename C::RedSmem& S, co
           io.frame_status[b] = ld_rlx(&ws.ctl->error) ? 5 : f.status;
         }
         if (t == NTr - 1) io.out_offsets[B] = (int64_t)excl;
+        publish_skipped<C>(ws, io, fd, j, nv, b, B, excl);
       }
     }
     return;
@@ -1450,6 +1464,7 @@ __device__ void red_tile(const Ws& ws, const GIo& io, typename C::RedSmem& S, co
         io.frame_status[b] = ld_rlx(&ws.ctl->error) ? 5 : f.status;
       }
       if (t == NTr - 1) io.out_offsets[B] = (int64_t)(excl + H);
+      publish_skipped<C>(ws, io, fd, j, nv, b, B, excl + H);
     }
   }
   __syncthreads();
@@ -1663,6 +1678,15 @@ __device__ __forceinline__ void next_item(const Ws& ws, const CallHdr& hdr, Bloc
       }
       return;
     }
+    if (ph == C::PH_RED) {
+      // past the frame's valid points: skip the frame's remaining tiles (their
+      // row prefix comes from the frame's last tile with points)
+      const int64_t nv = f.status == kFrameOk ? (int64_t)f.n_valid : 0;
+      if (j > 0 && (int64_t)j * C::TR >= nv) {
+        atomicMax(counter, base + (uint32_t)(fd.tr0 + fd.ntr));
+        continue;
+      }
+    }
     // reduce: the frame's last radix pass must be complete
     if (bc.dep_b[ph] != b) {
       if (persistent && f.passes > 0 && f.status == kFrameOk) {
@@ -1831,8 +1855,12 @@ __global__ __launch_bounds__(C::BLOCK, (kMinWaves<C, KIND>)) void vg_pipeline_ke
           if (persistent) {
             __syncthreads();
             if (threadIdx.x == 0) {
+              // the frame's last tile with points also counts its skipped tiles
+              const int64_t nv = f.status == kFrameOk ? (int64_t)f.n_valid : 0;
+              const int jl = nv > 0 ? (int)((nv - 1) / C::TR) : 0;
+              const uint32_t skipped = j == jl ? (uint32_t)(fd.ntr - jl - 1) : 0u;
               fence_rel();
-              atomicAdd(&ws.ctl->red_tiles_done, 1u);
+              atomicAdd(&ws.ctl->red_tiles_done, 1u + skipped);
             }
           }
         }
