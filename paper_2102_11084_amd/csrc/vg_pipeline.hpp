@@ -1761,18 +1761,43 @@ __global__ __launch_bounds__(C::BLOCK, (kMinWaves<C, KIND>)) void vg_pipeline_ke
   const bool own_order = cache && !multi && ph_lo >= C::PH_SORT0 && ph_lo < C::PH_RED &&
                          hdr.ilv_rounds > 0 && hdr.B <= kIlvMaxFrames;
   if (own_order) {
-    // keep the host order (frames by descending sort-tile count) of just the
-    // frames that need this pass, then count the frames of every round
+    // the frames that need this pass, by descending count of tiles to run
+    // (after the first pass, tiles past a frame's valid points have nothing
+    // to do and are left out), ties in the host order; then the frames of
+    // every round.  Scratch: tp[0] counts in host order, tp[1] the frames and
+    // tp[2] the counts in the new order (one-pass radix launches use neither
+    // tile prefix table).
     __syncthreads();
     const int p = ph_lo - C::PH_SORT0;
     const int i = threadIdx.x;
-    const uint32_t fr = (i < hdr.B) ? bc.ilv_perm[i] : 0u;
-    const uint32_t keep = (i < hdr.B && bc.fpa[fr].passes > p) ? 1u : 0u;
-    uint32_t nkeep;
-    const uint32_t pos = block_excl_scan<C::BLOCK>(keep, bc.scan_w, nkeep);
-    if (keep) bc.tp[0][pos] = fr;  // the big-tile prefixes are not used by radix launches
+    uint32_t my = 0;
+    uint32_t fr = 0;
+    if (i < hdr.B) {
+      fr = bc.ilv_perm[i];
+      const FrameParams& fp = bc.fpa[fr];
+      const uint32_t nts = (uint32_t)bc.fda[fr].nts;
+      if (fp.passes > p) {
+        my = nts;
+        if (p > 0) my = min(nts, (uint32_t)((fp.n_valid + C::TS - 1) / C::TS));
+      }
+      bc.tp[0][i] = my;
+    }
     __syncthreads();
-    const int rounds = nkeep ? bc.fda[bc.tp[0][0]].nts : 0;  // the first frame has the most
+    uint32_t nkeep = 0, rank = 0;
+    for (int k = 0; k < hdr.B; ++k) {
+      const uint32_t o = bc.tp[0][k];
+      nkeep += o > 0 ? 1u : 0u;
+      rank += (o > my || (o == my && k < i)) ? 1u : 0u;
+    }
+    if (my > 0) {
+      bc.tp[1][rank] = fr;
+      bc.tp[2][rank] = my;
+      // the tiles left out still count as done, for launches that wait on them
+      if (blockIdx.x == 0 && my < (uint32_t)bc.fda[fr].nts)
+        atomicAdd(&ws.fs[fr].pass_done[p], (uint32_t)bc.fda[fr].nts - my);
+    }
+    __syncthreads();
+    const int rounds = nkeep ? (int)bc.tp[2][0] : 0;
     // cnt(r) = kept frames with more than r tiles; ilv_s = exclusive prefix of cnt
     constexpr int PER = (kIlvMaxRounds + C::BLOCK - 1) / C::BLOCK;
     uint32_t cnts[PER];
@@ -1782,7 +1807,7 @@ __global__ __launch_bounds__(C::BLOCK, (kMinWaves<C, KIND>)) void vg_pipeline_ke
       const int r = i * PER + q;
       uint32_t c = 0;
       if (r < rounds)
-        for (uint32_t k = 0; k < nkeep; ++k) c += (bc.fda[bc.tp[0][k]].nts > r) ? 1u : 0u;
+        for (uint32_t k = 0; k < nkeep; ++k) c += (bc.tp[2][k] > (uint32_t)r) ? 1u : 0u;
       cnts[q] = c;
       mysum += c;
     }
@@ -1794,7 +1819,7 @@ __global__ __launch_bounds__(C::BLOCK, (kMinWaves<C, KIND>)) void vg_pipeline_ke
       if (r < rounds) bc.ilv_s[r] = run;
       run += cnts[q];
     }
-    for (int k = i; k < (int)nkeep; k += C::BLOCK) bc.ilv_perm[k] = bc.tp[0][k];
+    for (int k = i; k < (int)nkeep; k += C::BLOCK) bc.ilv_perm[k] = bc.tp[1][k];
     if (i == 0) {
       bc.ilv_s[rounds] = total_items;
       bc.ilv_rounds = rounds;
