@@ -260,11 +260,12 @@ def main():
         "data": "synthetic (seeded ray-cast RGB-D frames standing in for the paper's corridor data)",
         "config": {
             "workload": f"batched: {len(leaves)} uneven RGB-D frames, 50k-900k valid points each, "
-                        "per-frame leaf in {0.02, 0.05, 0.10} m, one persistent launch replayed "
-                        "from a hipGraph",
+                        "per-frame leaf in {0.02, 0.05, 0.10} m, one call per step, its launch "
+                        "sequence (one launch per phase in the tuned form) replayed from a hipGraph",
             "frames": int(len(leaves)), "points": N, "valid_points": int(nv_frames.sum()),
             "cells": int(m_frames.sum()), "radix_passes": [int(p) for p in passes],
             "tuning": tuning.as_dict(), "graph": not args.no_graph, "outputs": list(out_set),
+            "launch_form": "persistent" if tuning.exec_mode == vg.EXEC_PERSISTENT else "phased",
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
