@@ -376,7 +376,6 @@ struct Cfg {
     uint32_t hi[TS];
     uint32_t idx[TS];
     uint32_t wcnt[NW][R];
-    uint32_t tstart[R];
     uint32_t gbase[R];
     uint32_t dstart[R];
     uint32_t wsum[NW];
@@ -887,7 +886,7 @@ __device__ void stream_big_tiles(const Ws& ws, const GIo& io, const CallHdr& hdr
 template <class C>
 __device__ void sort_tile(const Ws& ws, const GIo& io, typename C::SortSmem& S, const FrameDesc& fd,
                           int b, int j, int p, const FrameParams& f, int key_mode,
-                          bool persistent) {
+                          bool persistent, uint32_t* claim, bool& have_pre, uint32_t& pre) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int Rb = 1 << f.w;
   const uint32_t mask = (uint32_t)Rb - 1u;
@@ -973,25 +972,41 @@ __device__ void sort_tile(const Ws& ws, const GIo& io, typename C::SortSmem& S, 
   }
   __syncthreads();
 
-  // rank every item among equal digits of its wave, in input order
+  // rank every item among equal digits of its wave, in input order: the
+  // lanes with an equal digit (one ballot per digit bit), then one LDS add per
+  // distinct digit, by the group's lowest lane.  A wave's LDS operations take
+  // effect in issue order, so the count each add returns is the number of
+  // equal digits in the wave's earlier items; the other lanes of the group read
+  // it from the lowest lane.
   uint32_t rank[C::SI], dg[C::SI];
 #pragma unroll
   for (int it = 0; it < C::SI; ++it) {
     const bool valid = (vm >> it) & 1u;
     const uint32_t d = digit_of(klo[it], khi[it], shift, mask);
     dg[it] = d;
-    uint64_t match = __ballot(valid);
+    const uint64_t vb = __ballot(valid);
+    uint32_t mlo = (uint32_t)vb, mhi = (uint32_t)(vb >> 32);
+    const uint32_t nd = ~d;
     for (int bit = 0; bit < f.w; ++bit) {
-      const bool set = (d >> bit) & 1u;
-      const uint64_t bal = __ballot(set);
-      match &= set ? bal : ~bal;
+      const uint32_t clr = (uint32_t)(((int32_t)(nd << (31 - bit))) >> 31);  // ~0 where the bit is 0
+      const uint64_t bal = __ballot(clr == 0u);
+      mlo &= (uint32_t)bal ^ clr;
+      mhi &= (uint32_t)(bal >> 32) ^ clr;
     }
-    const uint32_t below = lanes_below(match);
-    const uint32_t cnt = (uint32_t)__popcll(match);
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi(mhi, __builtin_amdgcn_mbcnt_lo(mlo, 0u));
     uint32_t pre = 0;
-    if (valid) pre = S.wcnt[w][d];
-    if (valid && below == 0) S.wcnt[w][d] = pre + cnt;
-    rank[it] = pre + below;
+    if (valid && below == 0)
+      pre = atomicAdd(&S.wcnt[w][d], (uint32_t)(__popc(mlo) + __popc(mhi)));
+    // lowest lane of the group, and this lane's place after it
+    const uint32_t lead = mlo ? (uint32_t)__builtin_ctz(mlo) : 32u + (uint32_t)__builtin_ctz(mhi | 0x80000000u);
+    rank[it] = pre;
+    dg[it] |= (lead << 16) | (below << 24);
+  }
+#pragma unroll
+  for (int it = 0; it < C::SI; ++it) {
+    const uint32_t lead = (dg[it] >> 16) & 0xffu;
+    rank[it] = (uint32_t)__shfl((int)rank[it], (int)lead) + (dg[it] >> 24);
+    dg[it] &= 0xffffu;
   }
   __syncthreads();
 
@@ -1007,52 +1022,102 @@ __device__ void sort_tile(const Ws& ws, const GIo& io, typename C::SortSmem& S, 
   }
   uint32_t tile_total;
   const uint32_t tex = block_excl_scan<C::BLOCK>(tcnt, S.wsum, tile_total);
-  if ((int)threadIdx.x < C::R) S.tstart[threadIdx.x] = tex;
-
-  // decoupled look-back over the frame's earlier tiles of this pass
   if ((int)threadIdx.x < Rb) {
+    // S.wcnt[w][d] becomes the tile place of wave w's first item of digit d
     const int d = threadIdx.x;
-    uint32_t* mine = ws.sdesc + ((size_t)p * ws.capNTs + t) * C::R + d;
-    uint32_t excl = 0;
-    if (j == 0) {
-      st_rlx(mine, kFlagP32 | tcnt);
-    } else {
-      st_rlx(mine, kFlagA32 | tcnt);
-      excl = look_back32(ws.sdesc + (size_t)p * ws.capNTs * C::R + d, C::R, t - 1, fd.ts0,
-                         ws.ctl);
-      st_rlx(mine, kFlagP32 | ((excl + tcnt) & kVal32));
-    }
-    S.gbase[d] = S.dstart[d] + excl;
+    for (int i = 0; i < C::NW; ++i) S.wcnt[i][d] += tex;
   }
+  const int t_mine = t;
+  // publish this tile's digit counts before anything else
+  if ((int)threadIdx.x < Rb)
+    st_rlx(ws.sdesc + ((size_t)p * ws.capNTs + t_mine) * C::R + threadIdx.x,
+           (j == 0 ? kFlagP32 : kFlagA32) | tcnt);
   __syncthreads();
 
   // stage the tile in LDS in digit order
+  {
+    uint32_t lp[C::SI];
 #pragma unroll
-  for (int it = 0; it < C::SI; ++it) {
-    if ((vm >> it) & 1u) {
-      const uint32_t d = dg[it];
-      const uint32_t lp = S.tstart[d] + S.wcnt[w][d] + rank[it];
-      S.lo[lp] = klo[it];
-      S.hi[lp] = khi[it];
-      S.idx[lp] = kid[it];
+    for (int it = 0; it < C::SI; ++it) lp[it] = S.wcnt[w][dg[it]] + rank[it];
+    if (f.wide) {
+#pragma unroll
+      for (int it = 0; it < C::SI; ++it)
+        if ((vm >> it) & 1u) {
+          S.lo[lp[it]] = klo[it];
+          S.hi[lp[it]] = khi[it];
+          S.idx[lp[it]] = kid[it];
+        }
+    } else {
+#pragma unroll
+      for (int it = 0; it < C::SI; ++it)
+        if ((vm >> it) & 1u) {
+          S.lo[lp[it]] = klo[it];
+          S.idx[lp[it]] = kid[it];
+        }
     }
   }
+
+  // decoupled look-back over the frame's earlier tiles of this pass; gbase[d]
+  // becomes the global place of digit d's run minus its place in the tile
+  if ((int)threadIdx.x < Rb) {
+    const int d = threadIdx.x;
+    uint32_t excl = 0;
+    if (j > 0) {
+      uint32_t* mine = ws.sdesc + ((size_t)p * ws.capNTs + t_mine) * C::R + d;
+      excl = look_back32(ws.sdesc + (size_t)p * ws.capNTs * C::R + d, C::R, t_mine - 1, fd.ts0,
+                         ws.ctl);
+      st_rlx(mine, kFlagP32 | ((excl + tcnt) & kVal32));
+    }
+    S.gbase[d] = S.dstart[d] + excl - tex;
+  }
   __syncthreads();
+  if (claim != nullptr && threadIdx.x == 0) {
+    pre = atomicAdd(claim, 1u);
+    have_pre = true;
+  }
 
   // write runs of equal digits to their global places
   const int dst = (p + 1) & 1;
   uint32_t* dlo = ws.lo[dst] + fd.off;
   uint32_t* dhi = ws.hi[dst] + fd.off;
   uint32_t* did = ws.idx[dst] + fd.off;
-  for (uint32_t i = threadIdx.x; i < tile_total; i += C::BLOCK) {
-    const uint32_t lo = S.lo[i], hi = S.hi[i];
-    const uint32_t d = digit_of(lo, hi, shift, mask);
-    const uint32_t gp = S.gbase[d] + (i - S.tstart[d]);
-    if (gp < (uint32_t)fd.n) {
-      dlo[gp] = lo;
-      if (f.wide) dhi[gp] = hi;
-      did[gp] = S.idx[i];
+  const uint32_t nlim = (uint32_t)fd.n;
+  if (f.wide) {
+    uint32_t lo[C::SI], hi[C::SI], id[C::SI], gp[C::SI];
+#pragma unroll
+    for (int k = 0; k < C::SI; ++k) {
+      const uint32_t i = threadIdx.x + k * C::BLOCK;
+      lo[k] = S.lo[i];
+      hi[k] = S.hi[i];
+      id[k] = S.idx[i];
     }
+#pragma unroll
+    for (int k = 0; k < C::SI; ++k)
+      gp[k] = S.gbase[digit_of(lo[k], hi[k], shift, mask)] + threadIdx.x + k * C::BLOCK;
+#pragma unroll
+    for (int k = 0; k < C::SI; ++k)
+      if (threadIdx.x + k * C::BLOCK < tile_total && gp[k] < nlim) {
+        dlo[gp[k]] = lo[k];
+        dhi[gp[k]] = hi[k];
+        did[gp[k]] = id[k];
+      }
+  } else {
+    uint32_t lo[C::SI], id[C::SI], gp[C::SI];
+#pragma unroll
+    for (int k = 0; k < C::SI; ++k) {
+      const uint32_t i = threadIdx.x + k * C::BLOCK;
+      lo[k] = S.lo[i];
+      id[k] = S.idx[i];
+    }
+#pragma unroll
+    for (int k = 0; k < C::SI; ++k)
+      gp[k] = S.gbase[(lo[k] >> shift) & mask] + threadIdx.x + k * C::BLOCK;
+#pragma unroll
+    for (int k = 0; k < C::SI; ++k)
+      if (threadIdx.x + k * C::BLOCK < tile_total && gp[k] < nlim) {
+        dlo[gp[k]] = lo[k];
+        did[gp[k]] = id[k];
+      }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -1550,15 +1615,37 @@ __device__ void red_tile(const Ws& ws, const GIo& io, typename C::RedSmem& S, co
 // its inputs (once per frame and phase), prepare the frame's grid parameters.
 // A launch of several radix passes (`multi`, not `persistent`) numbers its
 // items pass after pass; a tile of pass p waits for pass p - 1 of its frame.
+// Largest k in [0, n) with a[k] <= v, for a non-decreasing LDS table with
+// a[0] <= v and n <= 4096: each lane of the wave probes one entry of a coarse
+// grid, then one entry of the chosen interval; a ballot finds the last entry
+// that is <= v at each level.  Every wave gets the same answer.
+__device__ __forceinline__ int wave_search(const uint32_t* a, int n, uint32_t v) {
+  const int lane = threadIdx.x & 63;
+  const int step = (n + 63) >> 6;
+  const int i1 = lane * step;
+  const uint64_t m1 = __ballot(i1 < n && a[i1] <= v);
+  int k = (63 - __clzll((long long)m1)) * step;
+  if (step > 1) {
+    const int i2 = k + lane;
+    const uint64_t m2 = __ballot(lane < step && i2 < n && a[i2] <= v);
+    k += 63 - __clzll((long long)m2);
+  }
+  return k;
+}
+
 template <class C>
 __device__ __forceinline__ void next_item(const Ws& ws, const CallHdr& hdr, BlockCtl& bc,
                                        uint32_t* counter, bool persistent, bool multi, int ph_lo,
-                                       uint32_t total, bool stat, uint32_t& sitem) {
+                                       uint32_t total, bool stat, uint32_t& sitem, bool& have_pre,
+                                       uint32_t pre) {
   for (;;) {
     uint32_t item;
     if (stat) {  // tiles that wait on no tile: a fixed order
       item = sitem;
       sitem += gridDim.x;
+    } else if (have_pre) {  // claimed during the previous tile
+      item = pre;
+      have_pre = false;
     } else {
       item = atomicAdd(counter, 1u);
     }
@@ -1846,33 +1933,99 @@ __global__ __launch_bounds__(C::BLOCK, (kMinWaves<C, KIND>)) void vg_pipeline_ke
       return;
     }
   }
+  // One-phase radix (in their own order), reduce and fix-up launches with
+  // every frame's tables in LDS take the fast dispatch: thread 0 only takes
+  // the ticket, and every wave decodes it by itself, so a tile starts one
+  // barrier after its ticket.  Radix tiles there claim their next ticket once
+  // past their look-back (only the scatter is left, which waits on no tile),
+  // so the claim's latency overlaps the scatter.  Other launches go through
+  // next_item on thread 0.
+  const bool fast = cache && !persistent && !multi &&
+                    (KIND == kSort ? own_order : (KIND == kRed || KIND == kFix));
   // fix-up tiles only read what the reduce launch wrote: workgroup g takes
   // items g, g + G, ... instead of queue tickets
   const bool stat = !persistent && KIND == kFix;
   uint32_t sitem = blockIdx.x;
+  uint32_t* const claim = fast && KIND == kSort ? counter : nullptr;
+  bool have_pre = false;
+  uint32_t pre = 0;
   for (;;) {
-    if (threadIdx.x == 0)
-      next_item<C>(ws, hdr, bc, counter, persistent, multi, ph_lo, total, stat, sitem);
+    if (threadIdx.x == 0) {
+      if (fast) {
+        uint32_t item;
+        if (stat) {
+          item = sitem;
+          sitem += gridDim.x;
+        } else if (have_pre) {
+          item = pre;
+          have_pre = false;
+        } else {
+          item = atomicAdd(counter, 1u);
+        }
+        bc.item = item;
+      } else {
+        next_item<C>(ws, hdr, bc, counter, persistent, multi, ph_lo, total, stat, sitem, have_pre,
+                     pre);
+      }
+    }
     __syncthreads();
-    if (bc.item >= total) break;
-    const int ph = bc.ph, b = bc.b, j = bc.j;
-    const FrameDesc fd = bc.fd;
+    const uint32_t item = bc.item;
+    if (item >= total) break;
+    int ph, t, b, j;
+    const FrameDesc* fdp;
+    const FrameParams* fpp;
+    if (fast) {
+      ph = ph_lo;
+      t = (int)item;
+      if (KIND == kSort) {
+        j = wave_search(bc.ilv_s, bc.ilv_rounds, item);
+        b = (int)bc.ilv_perm[item - bc.ilv_s[j]];
+      } else if (KIND == kRed) {
+        b = wave_search(bc.tp[2], hdr.B, item);
+        j = (int)(item - bc.tp[2][b]);
+      } else {
+        b = 0;
+        j = 0;
+      }
+      fdp = &bc.fda[b];
+      fpp = &bc.fpa[b];
+      if (KIND == kRed) {
+        const int64_t nv = fpp->status == kFrameOk ? (int64_t)fpp->n_valid : 0;
+        if (j > 0 && (int64_t)j * C::TR >= nv) {
+          // past the frame's valid points: jump the queue past the frame's
+          // remaining tiles (their row prefix comes from its last tile with
+          // points)
+          if (threadIdx.x == 0) atomicMax(counter, (uint32_t)(fdp->tr0 + fdp->ntr));
+          __syncthreads();
+          continue;
+        }
+      }
+    } else {
+      ph = bc.ph;
+      t = bc.t;
+      b = bc.b;
+      j = bc.j;
+      fdp = &bc.fd;
+      fpp = &bc.fp;
+    }
+    const FrameDesc fd = *fdp;
     if (ph == C::PH_BBOX) {
       if constexpr (KIND == kAll || KIND == kBbox)
         bbox_tile<C>(ws, io, sm.bbox, fd, b, j, hdr.want, persistent);
     } else if (ph == C::PH_FIX) {
       if constexpr (KIND == kAll || KIND == kFix) {
-        const int t = bc.t * C::NW + (int)(threadIdx.x >> 6);
-        if (t < hdr.NTr) fix_tile<C>(ws, io, t, hdr.key_mode, hdr.want, hdr.N);
+        const int tf = t * C::NW + (int)(threadIdx.x >> 6);
+        if (tf < hdr.NTr) fix_tile<C>(ws, io, tf, hdr.key_mode, hdr.want, hdr.N);
       }
     } else {
-      const FrameParams f = bc.fp;
+      const FrameParams f = *fpp;
       if (ph == C::PH_HIST) {
         if constexpr (KIND == kAll || KIND == kHist)
           hist_tile<C>(ws, io, sm.hist, fd, b, j, f, hdr.key_mode, hdr.want, persistent);
       } else if (ph < C::PH_RED) {
         if constexpr (KIND == kAll || KIND == kSort)
-          sort_tile<C>(ws, io, sm.sort, fd, b, j, ph - C::PH_SORT0, f, hdr.key_mode, multi);
+          sort_tile<C>(ws, io, sm.sort, fd, b, j, ph - C::PH_SORT0, f, hdr.key_mode, multi, claim,
+                       have_pre, pre);
       } else {
         if constexpr (KIND == kAll || KIND == kRed) {
           red_tile<C>(ws, io, sm.red, fd, b, j, f, hdr.key_mode, hdr.want, hdr.B, hdr.NTr, hdr.N,
