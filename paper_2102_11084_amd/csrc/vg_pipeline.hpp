@@ -544,6 +544,15 @@ constexpr int kStreamBatch = KIND == kBbox ? 4 : 8;
 
 // A value every lane of the wave holds alike (read from LDS at a uniform
 // address), moved to scalar registers.
+// One word per lane from global memory straight into LDS: lane l of the wave
+// writes dst[l] (dst is the same for the whole wave).  The data is in LDS once
+// the wave's vector memory loads have completed (lds_load_wait).
+__device__ __forceinline__ void lds_load_word(const uint32_t* src, uint32_t* dst) {
+  __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                   (__attribute__((address_space(3))) void*)dst, 4, 0, 0);
+}
+__device__ __forceinline__ void lds_load_wait() { __builtin_amdgcn_s_waitcnt(0); }
+
 template <class T>
 __device__ __forceinline__ T wave_uniform(const T& v) {
   static_assert(sizeof(T) % 4 == 0, "whole dwords");
@@ -1393,46 +1402,46 @@ __device__ void red_tile(const Ws& ws, const GIo& io, typename C::RedSmem& S, co
     return;
   }
 
-  // ---- keys and indices to LDS with lane-consecutive (coalesced) loads; each
+  // ---- keys and indices straight into LDS (global-to-LDS loads: lane l of
+  // a wave fills word l of the wave's 64-word slot, no registers held); each
   // thread then owns items i*K .. i*K+K-1 of the tile (blocked) and gathers
-  // their points into registers
+  // their points into registers.  Addresses are clamped into the tile, so the
+  // slots past its items hold copies of the last one.
   {
     const int64_t lastp = e0 - 1;
+    const int wo = w * 64;
 #pragma unroll
     for (int u = 0; u < K; ++u) {
-      const int li = u * C::BLOCK + (int)threadIdx.x;
-      const int64_t pos = min(s0 + li, lastp);
-      const uint32_t lo = klo[pos];
-      const uint32_t id = min(kid[pos], Nm1);
-      if (li < cnt) {
-        S.klo[li] = lo;
-        S.kid[li] = id;
-      }
+      const int64_t pos = min(s0 + u * C::BLOCK + (int)threadIdx.x, lastp);
+      lds_load_word(klo + pos, &S.klo[u * C::BLOCK + wo]);
+      lds_load_word(kid + pos, &S.kid[u * C::BLOCK + wo]);
     }
     if (f.wide) {
 #pragma unroll
-      for (int u = 0; u < K; ++u) {
-        const int li = u * C::BLOCK + (int)threadIdx.x;
-        const uint32_t hi = khi[min(s0 + li, lastp)];
-        if (li < cnt) S.khi[li] = hi;
-      }
+      for (int u = 0; u < K; ++u)
+        lds_load_word(khi + min(s0 + u * C::BLOCK + (int)threadIdx.x, lastp),
+                      &S.khi[u * C::BLOCK + wo]);
     }
   }
   if (threadIdx.x == 0) {
     // the keys just before and just after the tile
+    const int64_t ip = s0 > 0 ? s0 - 1 : s0;
+    const int64_t in = e0 < nv ? e0 : e0 - 1;
+    const uint32_t plo = klo[ip], phi = khi[ip], nlo = klo[in], nhi = khi[in];
     S.has_prev = s0 > 0 ? 1u : 0u;
-    S.prev_lo = s0 > 0 ? klo[s0 - 1] : 0u;
-    S.prev_hi = (s0 > 0 && f.wide) ? khi[s0 - 1] : 0u;
+    S.prev_lo = s0 > 0 ? plo : 0u;
+    S.prev_hi = (s0 > 0 && f.wide) ? phi : 0u;
     S.has_next = e0 < nv ? 1u : 0u;
-    S.next_lo = e0 < nv ? klo[e0] : 0u;
-    S.next_hi = (e0 < nv && f.wide) ? khi[e0] : 0u;
+    S.next_lo = e0 < nv ? nlo : 0u;
+    S.next_hi = (e0 < nv && f.wide) ? nhi : 0u;
   }
+  lds_load_wait();
   __syncthreads();
   float px[K], py[K], pz[K];
   uint32_t c24[K];
 #pragma unroll
   for (int i = 0; i < K; ++i) {
-    const uint32_t id = S.kid[min(base + i, cnt - 1)];
+    const uint32_t id = min(S.kid[min(base + i, cnt - 1)], Nm1);
     const float4 r4 = ws.rec[id];
     px[i] = r4.x;
     py[i] = r4.y;
@@ -1558,7 +1567,8 @@ __device__ void red_tile(const Ws& ws, const GIo& io, typename C::RedSmem& S, co
         for (int a = 0; a < 3; ++a) dv[a] = __fsub_rn(p[a], r[a]);
         acc_add(c2, dv, c24[i]);
       }
-      if (want & kOutPointCell) io.point_cell[S.kid[base + i]] = (int32_t)(excl_t + hb + lh - 1);
+      if (want & kOutPointCell)
+        io.point_cell[min(S.kid[base + i], Nm1)] = (int32_t)(excl_t + hb + lh - 1);
     }
   }
 
