@@ -1437,18 +1437,6 @@ __device__ void red_tile(const Ws& ws, const GIo& io, typename C::RedSmem& S, co
   }
   lds_load_wait();
   __syncthreads();
-  float px[K], py[K], pz[K];
-  uint32_t c24[K];
-#pragma unroll
-  for (int i = 0; i < K; ++i) {
-    const uint32_t id = min(S.kid[min(base + i, cnt - 1)], Nm1);
-    const float4 r4 = ws.rec[id];
-    px[i] = r4.x;
-    py[i] = r4.y;
-    pz[i] = r4.z;
-    c24[i] = __float_as_uint(r4.w);
-  }
-
   // ---- head flags: an item starts a cell when its key differs from the previous one
   uint32_t vmask = 0, hmask = 0;
 #pragma unroll
@@ -1474,33 +1462,67 @@ __device__ void red_tile(const Ws& ws, const GIo& io, typename C::RedSmem& S, co
       if ((hmask >> i) & 1u) S.hpos[r++] = (uint16_t)(base + i);
   }
 
-  // ---- publish the tile's head count at once; the look-back for the rows
-  // before it waits until the sums are done, so earlier tiles have had time
-  // to publish their prefixes
+  // ---- publish the tile's head count at once
   if (threadIdx.x == 0) st_rlx64(&ws.rdesc[t], (t == 0 ? kFlagP64 : kFlagA64) | H);
 
-  // ---- per-item values: the thread's open ends (sums before its first head,
-  // and from its last head on)
+  // ---- gather the thread's points; they arrive during the look-back
+  float px[K], py[K], pz[K];
+  uint32_t c24[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    const uint32_t id = min(S.kid[min(base + i, cnt - 1)], Nm1);
+    const float4 r4 = ws.rec[id];
+    px[i] = r4.x;
+    py[i] = r4.y;
+    pz[i] = r4.z;
+    c24[i] = __float_as_uint(r4.w);
+  }
+
+  // ---- look-back over head counts: dense rows across frames
+  if (threadIdx.x < 64) {
+    uint64_t excl = 0;
+    if (t > 0) excl = look_back64_wave(ws.rdesc, t - 1, ws.ctl);
+    if (threadIdx.x == 0) {
+      if (t > 0) st_rlx64(&ws.rdesc[t], kFlagP64 | (excl + H));
+      S.excl = excl;
+      if (j == 0) {
+        io.out_offsets[b] = (int64_t)excl;
+        io.frame_status[b] = ld_rlx(&ws.ctl->error) ? 5 : f.status;
+      }
+      if (t == NTr - 1) io.out_offsets[B] = (int64_t)(excl + H);
+      publish_skipped<C>(ws, io, fd, j, nv, b, B, excl + H);
+    }
+  }
+  __syncthreads();
+  const int64_t excl_t = (int64_t)S.excl;
+
+  // ---- one pass over the thread's items: the open ends (sums before its
+  // first head, and from its last head on) and every cell that opens and
+  // closes inside the thread, written at once; the row of each point
   Acc pre, cur;
   acc_zero(pre);
   acc_zero(cur);
-  bool seen_head = false;
+  uint32_t lh = 0;  // heads seen
 #pragma unroll
   for (int i = 0; i < K; ++i) {
     if (!((vmask >> i) & 1u)) continue;
+    if ((hmask >> i) & 1u) {
+      if (lh == 0) pre = cur;
+      else
+        finalize_row(io, want, excl_t + hb + lh - 1, N, cur, nullptr,
+                     cell_at<C>(S, f, key_mode, S.hpos[hb + lh - 1]));
+      acc_zero(cur);
+      ++lh;
+    }
     const float p[3] = {px[i], py[i], pz[i]};
     float r[3], dv[3];
     corner_of(f, p, r);
     for (int a = 0; a < 3; ++a) dv[a] = __fsub_rn(p[a], r[a]);
-    if ((hmask >> i) & 1u) {
-      if (!seen_head) {
-        pre = cur;
-        seen_head = true;
-      }
-      acc_zero(cur);
-    }
     acc_add(cur, dv, c24[i]);
+    if (want & kOutPointCell)
+      io.point_cell[min(S.kid[base + i], Nm1)] = (int32_t)(excl_t + hb + lh - 1);
   }
+  const bool seen_head = lh > 0;
   if (!seen_head) pre = cur;
 
   // ---- block segmented scan of the threads' open ends
@@ -1525,52 +1547,6 @@ __device__ void red_tile(const Ws& ws, const GIo& io, typename C::RedSmem& S, co
     acc_zero(ex.a);
   }
   ex = seg_combine(wp, ex);
-
-  // ---- look-back over head counts: dense rows across frames
-  if (threadIdx.x < 64) {
-    uint64_t excl = 0;
-    if (t > 0) excl = look_back64_wave(ws.rdesc, t - 1, ws.ctl);
-    if (threadIdx.x == 0) {
-      if (t > 0) st_rlx64(&ws.rdesc[t], kFlagP64 | (excl + H));
-      S.excl = excl;
-      if (j == 0) {
-        io.out_offsets[b] = (int64_t)excl;
-        io.frame_status[b] = ld_rlx(&ws.ctl->error) ? 5 : f.status;
-      }
-      if (t == NTr - 1) io.out_offsets[B] = (int64_t)(excl + H);
-      publish_skipped<C>(ws, io, fd, j, nv, b, B, excl + H);
-    }
-  }
-  __syncthreads();
-  const int64_t excl_t = (int64_t)S.excl;
-
-  // ---- cells that open and close inside this thread, and the rows of its points
-  if (__popc(hmask) > 1 || (want & kOutPointCell)) {
-    Acc c2;
-    acc_zero(c2);
-    uint32_t lh = 0;
-#pragma unroll
-    for (int i = 0; i < K; ++i) {
-      if (!((vmask >> i) & 1u)) continue;
-      if ((hmask >> i) & 1u) {
-        if (lh > 0)
-          finalize_row(io, want, excl_t + hb + lh - 1, N, c2, nullptr,
-                       cell_at<C>(S, f, key_mode, S.hpos[hb + lh - 1]));
-        acc_zero(c2);
-        ++lh;
-      }
-      if (lh > 0 && ((hmask >> (i + 1)) & (vmask >> (i + 1))) != 0u) {
-        // a later head of this thread closes the cell: it needs the sums
-        const float p[3] = {px[i], py[i], pz[i]};
-        float r[3], dv[3];
-        corner_of(f, p, r);
-        for (int a = 0; a < 3; ++a) dv[a] = __fsub_rn(p[a], r[a]);
-        acc_add(c2, dv, c24[i]);
-      }
-      if (want & kOutPointCell)
-        io.point_cell[min(S.kid[base + i], Nm1)] = (int32_t)(excl_t + hb + lh - 1);
-    }
-  }
 
   // (i) the cell open at this thread's start closes at its first head
   if (seen_head) {
