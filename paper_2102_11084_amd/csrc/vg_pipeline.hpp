@@ -443,6 +443,7 @@ struct BlockCtl {
   int32_t cached;                    // one-phase launches after the bbox: every frame below
   FrameParams fpa[kFpCache];
   FrameDesc fda[kFpCache];
+  uint32_t vt0[kFpCache + 1];        // one-phase reduce: first row-count descriptor per frame
 };
 
 template <class C>
@@ -1367,7 +1368,7 @@ __device__ __forceinline__ void publish_skipped(const Ws& ws, const GIo& io, con
 template <class C>
 __device__ void red_tile(const Ws& ws, const GIo& io, typename C::RedSmem& S, const FrameDesc& fd,
                          int b, int j, const FrameParams& f, int key_mode, uint32_t want, int B,
-                         int NTr, int64_t N, bool persistent) {
+                         int NTr, int64_t N, bool persistent, int dt, int dlast, bool compact) {
   constexpr int K = C::RI;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int t = fd.tr0 + j;
@@ -1385,18 +1386,18 @@ __device__ void red_tile(const Ws& ws, const GIo& io, typename C::RedSmem& S, co
     // past the frame's valid points: only the row count chain goes on
     if (threadIdx.x < 64) {
       uint64_t excl = 0;
-      if (t > 0) {
-        if (threadIdx.x == 0) st_rlx64(&ws.rdesc[t], kFlagA64);
-        excl = look_back64_wave(ws.rdesc, t - 1, ws.ctl);
+      if (dt > 0) {
+        if (threadIdx.x == 0) st_rlx64(&ws.rdesc[dt], kFlagA64);
+        excl = look_back64_wave(ws.rdesc, dt - 1, ws.ctl);
       }
       if (threadIdx.x == 0) {
-        st_rlx64(&ws.rdesc[t], kFlagP64 | excl);
+        st_rlx64(&ws.rdesc[dt], kFlagP64 | excl);
         if (j == 0) {
           io.out_offsets[b] = (int64_t)excl;
           io.frame_status[b] = ld_rlx(&ws.ctl->error) ? 5 : f.status;
         }
-        if (t == NTr - 1) io.out_offsets[B] = (int64_t)excl;
-        publish_skipped<C>(ws, io, fd, j, nv, b, B, excl);
+        if (dt == dlast) io.out_offsets[B] = (int64_t)excl;
+        if (!compact) publish_skipped<C>(ws, io, fd, j, nv, b, B, excl);
       }
     }
     return;
@@ -1463,7 +1464,7 @@ __device__ void red_tile(const Ws& ws, const GIo& io, typename C::RedSmem& S, co
   }
 
   // ---- publish the tile's head count at once
-  if (threadIdx.x == 0) st_rlx64(&ws.rdesc[t], (t == 0 ? kFlagP64 : kFlagA64) | H);
+  if (threadIdx.x == 0) st_rlx64(&ws.rdesc[dt], (dt == 0 ? kFlagP64 : kFlagA64) | H);
 
   // ---- gather the thread's points; they arrive during the look-back
   float px[K], py[K], pz[K];
@@ -1481,16 +1482,16 @@ __device__ void red_tile(const Ws& ws, const GIo& io, typename C::RedSmem& S, co
   // ---- look-back over head counts: dense rows across frames
   if (threadIdx.x < 64) {
     uint64_t excl = 0;
-    if (t > 0) excl = look_back64_wave(ws.rdesc, t - 1, ws.ctl);
+    if (dt > 0) excl = look_back64_wave(ws.rdesc, dt - 1, ws.ctl);
     if (threadIdx.x == 0) {
-      if (t > 0) st_rlx64(&ws.rdesc[t], kFlagP64 | (excl + H));
+      if (dt > 0) st_rlx64(&ws.rdesc[dt], kFlagP64 | (excl + H));
       S.excl = excl;
       if (j == 0) {
         io.out_offsets[b] = (int64_t)excl;
         io.frame_status[b] = ld_rlx(&ws.ctl->error) ? 5 : f.status;
       }
-      if (t == NTr - 1) io.out_offsets[B] = (int64_t)(excl + H);
-      publish_skipped<C>(ws, io, fd, j, nv, b, B, excl + H);
+      if (dt == dlast) io.out_offsets[B] = (int64_t)(excl + H);
+      if (!compact) publish_skipped<C>(ws, io, fd, j, nv, b, B, excl + H);
     }
   }
   __syncthreads();
@@ -1829,6 +1830,24 @@ __global__ __launch_bounds__(C::BLOCK, (kMinWaves<C, KIND>)) void vg_pipeline_ke
     bc.cached = cache ? 1 : 0;
     bc.ilv_rounds = hdr.ilv_rounds;
   }
+  if constexpr (KIND == kRed) {
+    // A one-phase reduce launch skips the tiles past each frame's valid points,
+    // so its row-count chain runs over the other tiles only: frame b's tiles
+    // hold descriptors vt0[b] .. vt0[b+1]-1 (at least one per frame).
+    if (cache) {
+      __syncthreads();
+      uint32_t nvt = 0;
+      if ((int)threadIdx.x < hdr.B) {
+        const FrameParams& fp = bc.fpa[threadIdx.x];
+        const int64_t nv = fp.status == kFrameOk ? (int64_t)fp.n_valid : 0;
+        nvt = nv > 0 ? (uint32_t)((nv + C::TR - 1) / C::TR) : 1u;
+      }
+      uint32_t tot;
+      const uint32_t ex = block_excl_scan<C::BLOCK>(nvt, bc.scan_w, tot);
+      if ((int)threadIdx.x < hdr.B) bc.vt0[threadIdx.x] = ex;
+      if (threadIdx.x == 0) bc.vt0[hdr.B] = tot;
+    }
+  }
   // a one-pass radix launch with every frame's grid at hand orders its tiles
   // round-robin over just the frames that need this pass
   const bool own_order = cache && !multi && ph_lo >= C::PH_SORT0 && ph_lo < C::PH_RED &&
@@ -2014,8 +2033,10 @@ __global__ __launch_bounds__(C::BLOCK, (kMinWaves<C, KIND>)) void vg_pipeline_ke
                        have_pre, pre);
       } else {
         if constexpr (KIND == kAll || KIND == kRed) {
+          const int dt = fast ? (int)bc.vt0[b] + j : fd.tr0 + j;
+          const int dlast = fast ? (int)bc.vt0[hdr.B] - 1 : hdr.NTr - 1;
           red_tile<C>(ws, io, sm.red, fd, b, j, f, hdr.key_mode, hdr.want, hdr.B, hdr.NTr, hdr.N,
-                      persistent);
+                      persistent, dt, dlast, fast);
           if (persistent) {
             __syncthreads();
             if (threadIdx.x == 0) {
