@@ -73,17 +73,35 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// Lane moves within a wave by DPP (data-parallel primitives: a VALU operand
+// read from another lane, no LDS).  A row is 16 lanes.  row_shr:k (0x110+k)
+// reads the lane k below in the same row, 0 past the row start; row_bcast:15
+// (0x142) and row_bcast:31 (0x143) read lane 15 / 31 of the row block before,
+// into the rows that ROWS selects (the others read 0); wave_shr:1 (0x138)
+// reads the lane below across the whole wave, 0 for lane 0.
+template <int CTRL, int ROWS, bool BOUND>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, BOUND);
+}
+
+// Inclusive prefix sum over the lanes of a wave: within each row by shifts of
+// 1, 2, 4, 8, then across rows with the two broadcasts.
+__device__ __forceinline__ uint32_t wave_incl_add(uint32_t x) {
+  x += dpp_u32<0x111, 0xf, true>(x);
+  x += dpp_u32<0x112, 0xf, true>(x);
+  x += dpp_u32<0x114, 0xf, true>(x);
+  x += dpp_u32<0x118, 0xf, true>(x);
+  x += dpp_u32<0x142, 0xa, false>(x);
+  x += dpp_u32<0x143, 0xc, false>(x);
+  return x;
+}
+
 // Exclusive block scan of one u32 per thread; `wsum` holds NW words of LDS.
 template <int BLOCK>
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* wsum, uint32_t& total) {
   constexpr int NW = BLOCK / 64;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  uint32_t incl = v;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    uint32_t o = __shfl_up(incl, off);
-    if (lane >= off) incl += o;
-  }
+  const uint32_t incl = wave_incl_add(v);
   if (lane == 63) wsum[w] = incl;
   __syncthreads();
   uint32_t before = 0, tot = 0;
@@ -337,17 +355,32 @@ __device__ __forceinline__ Seg seg_combine(const Seg& x, const Seg& y) {
   return r;
 }
 
-__device__ __forceinline__ Seg seg_shfl_up(const Seg& v, int off) {
+// A Seg moved between lanes by one DPP control (see dpp_u32); lanes with no
+// source read the all-zero Seg, which seg_combine treats as an identity.
+template <int CTRL, int ROWS, bool BOUND>
+__device__ __forceinline__ Seg seg_dpp(const Seg& v) {
   Seg r;
-  r.f = __shfl_up(v.f, off);
-  r.a.n = __shfl_up(v.a.n, off);
+  r.f = dpp_u32<CTRL, ROWS, BOUND>(v.f);
+  r.a.n = dpp_u32<CTRL, ROWS, BOUND>(v.a.n);
   for (int i = 0; i < 3; ++i) {
-    r.a.s[i] = __shfl_up(v.a.s[i], off);
-    r.a.c[i] = __shfl_up(v.a.c[i], off);
+    r.a.s[i] = __uint_as_float(dpp_u32<CTRL, ROWS, BOUND>(__float_as_uint(v.a.s[i])));
+    r.a.c[i] = __uint_as_float(dpp_u32<CTRL, ROWS, BOUND>(__float_as_uint(v.a.c[i])));
   }
-  r.a.rgb = ((uint64_t)__shfl_up((uint32_t)(v.a.rgb >> 32), off) << 32) |
-            (uint32_t)__shfl_up((uint32_t)v.a.rgb, off);
+  r.a.rgb = ((uint64_t)dpp_u32<CTRL, ROWS, BOUND>((uint32_t)(v.a.rgb >> 32)) << 32) |
+            dpp_u32<CTRL, ROWS, BOUND>((uint32_t)v.a.rgb);
   return r;
+}
+
+// Inclusive segmented scan over the lanes of a wave (same steps as
+// wave_incl_add; the earlier lanes' Seg is always the left operand).
+__device__ __forceinline__ Seg wave_incl_seg(Seg x) {
+  x = seg_combine(seg_dpp<0x111, 0xf, true>(x), x);
+  x = seg_combine(seg_dpp<0x112, 0xf, true>(x), x);
+  x = seg_combine(seg_dpp<0x114, 0xf, true>(x), x);
+  x = seg_combine(seg_dpp<0x118, 0xf, true>(x), x);
+  x = seg_combine(seg_dpp<0x142, 0xa, false>(x), x);
+  x = seg_combine(seg_dpp<0x143, 0xc, false>(x), x);
+  return x;
 }
 
 // ---------------------------------------------------------- configs ----
@@ -715,8 +748,8 @@ __device__ __forceinline__ void hist_batch_fixed(const Ws& ws, typename C::HistS
     const uint32_t hi = WIDE && valid ? (uint32_t)(k >> 32) : 0u;
     if (!WIDE && f.narrow && inr) ws.lo[0][g0 + u * C::BLOCK + (int)threadIdx.x] = valid ? lo : kNoKey;
     const uint64_t vb = __ballot(valid);
-    const uint32_t plo = (uint32_t)__shfl_up((int)lo, 1);
-    const uint32_t phi = WIDE ? (uint32_t)__shfl_up((int)hi, 1) : 0u;
+    const uint32_t plo = dpp_u32<0x138, 0xf, true>(lo);  // the lane below's key
+    const uint32_t phi = WIDE ? dpp_u32<0x138, 0xf, true>(hi) : 0u;
     const bool prev_same = lane > 0 && ((vb >> (lane - 1)) & 1ull) && plo == lo && phi == hi;
     const bool head = valid && !prev_same;
     const uint64_t brk = __ballot(head) | ~vb;  // a run ends before a head or an invalid lane
@@ -1530,23 +1563,14 @@ __device__ void red_tile(const Ws& ws, const GIo& io, typename C::RedSmem& S, co
   Seg mine;
   mine.f = seen_head ? 1u : 0u;
   mine.a = seen_head ? cur : pre;
-  Seg incl = mine;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const Seg o = seg_shfl_up(incl, off);
-    if (lane >= off) incl = seg_combine(o, incl);
-  }
+  const Seg incl = wave_incl_seg(mine);
   if (lane == 63) S.wtot[w] = incl;
   __syncthreads();
   Seg wp;
   wp.f = 0;
   acc_zero(wp.a);
   for (int i = 0; i < w; ++i) wp = seg_combine(wp, S.wtot[i]);
-  Seg ex = seg_shfl_up(incl, 1);
-  if (lane == 0) {
-    ex.f = 0;
-    acc_zero(ex.a);
-  }
+  Seg ex = seg_dpp<0x138, 0xf, true>(incl);  // the lane below's inclusive value
   ex = seg_combine(wp, ex);
 
   // (i) the cell open at this thread's start closes at its first head
