@@ -116,6 +116,36 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* wsum, 
   return before + incl - v;
 }
 
+// Two exclusive block scans at once (one pair of barriers); `wsum` holds 2*NW
+// words of LDS.
+template <int BLOCK>
+__device__ __forceinline__ void block_excl_scan2(uint32_t va, uint32_t vb, uint32_t* wsum,
+                                                 uint32_t& ea, uint32_t& eb, uint32_t& ta,
+                                                 uint32_t& tb) {
+  constexpr int NW = BLOCK / 64;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t ia = wave_incl_add(va), ib = wave_incl_add(vb);
+  if (lane == 63) {
+    wsum[w] = ia;
+    wsum[NW + w] = ib;
+  }
+  __syncthreads();
+  uint32_t ba = 0, bb = 0, sa = 0, sb = 0;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    const uint32_t xa = wsum[k], xb = wsum[NW + k];
+    ba += (k < w) ? xa : 0u;
+    bb += (k < w) ? xb : 0u;
+    sa += xa;
+    sb += xb;
+  }
+  __syncthreads();
+  ea = ba + ia - va;
+  eb = bb + ib - vb;
+  ta = sa;
+  tb = sb;
+}
+
 // Decoupled look-back: sum the published values of tiles k0, k0-1, ... down
 // to the first inclusive prefix.  LB descriptors are read per round trip.
 constexpr int kLookBatchSort = 4;   // per digit, per round trip
@@ -410,8 +440,7 @@ struct Cfg {
     uint32_t idx[TS];
     uint32_t wcnt[NW][R];
     uint32_t gbase[R];
-    uint32_t dstart[R];
-    uint32_t wsum[NW];
+    uint32_t wsum[2 * NW];
   };
   struct HistSmem {
     uint32_t h[MAXP][R];
@@ -946,10 +975,12 @@ __device__ void sort_tile(const Ws& ws, const GIo& io, typename C::SortSmem& S, 
     return;
   }
 
-  // this pass's digit counts of the frame (scanned once the items are loaded)
+  // this pass's digit counts of the frame (scanned with the tile's counts)
   uint32_t hv = 0;
   if ((int)threadIdx.x < Rb) hv = ws.hist[((size_t)b * ws.slots + p) * C::R + threadIdx.x];
-  for (int i = threadIdx.x; i < C::NW * C::R; i += C::BLOCK) (&S.wcnt[0][0])[i] = 0u;
+  // this wave's digit counters (no other wave touches them before the
+  // barrier that ends the ranking)
+  for (int k = lane; k < C::R; k += 64) S.wcnt[w][k] = 0u;
 
   // items in wave-striped order: wave w owns 64*SI consecutive positions
   uint32_t klo[C::SI], khi[C::SI], kid[C::SI];
@@ -1007,14 +1038,6 @@ __device__ void sort_tile(const Ws& ws, const GIo& io, typename C::SortSmem& S, 
     for (int it = 0; it < C::SI; ++it)
       if (wbase + it * 64 < (int64_t)f.n_valid) vm |= 1u << it;
   }
-  // frame-wide digit offsets of this pass
-  {
-    uint32_t tot;
-    const uint32_t ex = block_excl_scan<C::BLOCK>(hv, S.wsum, tot);
-    if ((int)threadIdx.x < C::R) S.dstart[threadIdx.x] = ex;
-  }
-  __syncthreads();
-
   // rank every item among equal digits of its wave, in input order: the
   // lanes with an equal digit (one ballot per digit bit), then one LDS add per
   // distinct digit, by the group's lowest lane.  A wave's LDS operations take
@@ -1063,8 +1086,10 @@ __device__ void sort_tile(const Ws& ws, const GIo& io, typename C::SortSmem& S, 
       tcnt += v;
     }
   }
-  uint32_t tile_total;
-  const uint32_t tex = block_excl_scan<C::BLOCK>(tcnt, S.wsum, tile_total);
+  // the digit's place among this tile's items, and among the frame's items of
+  // this pass (from the frame's digit counts)
+  uint32_t tex, dex, tile_total, frame_total;
+  block_excl_scan2<C::BLOCK>(tcnt, hv, S.wsum, tex, dex, tile_total, frame_total);
   if ((int)threadIdx.x < Rb) {
     // S.wcnt[w][d] becomes the tile place of wave w's first item of digit d
     const int d = threadIdx.x;
@@ -1111,7 +1136,7 @@ __device__ void sort_tile(const Ws& ws, const GIo& io, typename C::SortSmem& S, 
                          ws.ctl);
       st_rlx(mine, kFlagP32 | ((excl + tcnt) & kVal32));
     }
-    S.gbase[d] = S.dstart[d] + excl - tex;
+    S.gbase[d] = dex + excl - tex;
   }
   __syncthreads();
   if (claim != nullptr && threadIdx.x == 0) {

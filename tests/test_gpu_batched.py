@@ -157,8 +157,10 @@ def test_full_uneven_batch_sampled():
 
 def many_frames(B, seed):
     """B uneven clouds: sizes 0..6000, some empty, some with NaN/Inf points,
-    leaves 0.02..0.2, one wide-key frame; exercises the paths for batches
-    beyond the frames whose tables and grids fit in LDS."""
+    leaves 0.02..0.2, one wide-key frame.  Batches of up to 64 frames take the
+    launches that keep every frame's tables and grid in LDS (one-pass radix
+    launches in their own order, the reduce's row chain over tiles with
+    points); larger ones exercise the other paths."""
     rng = np.random.default_rng(seed)
     xs, ys, zs, cs, sizes, leaves = [], [], [], [], [], []
     for b in range(B):
@@ -182,7 +184,7 @@ def many_frames(B, seed):
             np.array(leaves, np.float32))
 
 
-@pytest.mark.parametrize("B", [100, 300])
+@pytest.mark.parametrize("B", [60, 100, 300])
 def test_many_frames_match_per_frame_oracle(B):
     print(f"case batch of {B} frames", flush=True)
     x, y, z, rgb, offs, leaves = many_frames(B, seed=B)
