@@ -87,18 +87,20 @@ def kernel_bytes(n, nv, passes, m, narrow, point_cell=False):
 
 
 def source_digest():
-    """Digest of the device code, the header and the tuning file: counter
+    """Digest of the device code, the header and the tuning choice: counter
     figures taken under another digest no longer describe these kernels."""
     import hashlib
     h = hashlib.sha256()
-    files = [os.path.join(ROOT, "include", "vg.h"),
-             os.path.join(ROOT, "paper_2102_11084_amd", "tuning_gfx950.json")]
+    files = [os.path.join(ROOT, "include", "vg.h")]
     csrc = os.path.join(ROOT, "paper_2102_11084_amd", "csrc")
     files += [os.path.join(csrc, f) for f in sorted(os.listdir(csrc))
               if f.endswith((".hip", ".hpp", ".h"))]
     for f in files:
         with open(f, "rb") as fh:
             h.update(os.path.basename(f).encode() + b"\0" + fh.read())
+    # the tuning choice itself, not the timings the autotuner recorded with it
+    with open(os.path.join(ROOT, "paper_2102_11084_amd", "tuning_gfx950.json")) as fh:
+        h.update(b"tuning\0" + json.dumps(json.load(fh).get("tuning"), sort_keys=True).encode())
     return h.hexdigest()[:16]
 
 
