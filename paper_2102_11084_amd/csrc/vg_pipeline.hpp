@@ -1045,28 +1045,40 @@ __device__ void sort_tile(const Ws& ws, const GIo& io, typename C::SortSmem& S, 
   // equal digits in the wave's earlier items; the other lanes of the group read
   // it from the lowest lane.
   uint32_t rank[C::SI], dg[C::SI];
+  static_assert(C::SI % 2 == 0, "items ranked in pairs");
 #pragma unroll
-  for (int it = 0; it < C::SI; ++it) {
-    const bool valid = (vm >> it) & 1u;
-    const uint32_t d = digit_of(klo[it], khi[it], shift, mask);
-    dg[it] = d;
-    const uint64_t vb = __ballot(valid);
-    uint32_t mlo = (uint32_t)vb, mhi = (uint32_t)(vb >> 32);
-    const uint32_t nd = ~d;
+  for (int it = 0; it < C::SI; it += 2) {
+    // two items at a time: their ballot chains are independent
+    const bool v0 = (vm >> it) & 1u, v1 = (vm >> (it + 1)) & 1u;
+    const uint32_t d0 = digit_of(klo[it], khi[it], shift, mask);
+    const uint32_t d1 = digit_of(klo[it + 1], khi[it + 1], shift, mask);
+    const uint64_t vb0 = __ballot(v0), vb1 = __ballot(v1);
+    uint32_t m0lo = (uint32_t)vb0, m0hi = (uint32_t)(vb0 >> 32);
+    uint32_t m1lo = (uint32_t)vb1, m1hi = (uint32_t)(vb1 >> 32);
+    const uint32_t nd0 = ~d0, nd1 = ~d1;
     for (int bit = 0; bit < f.w; ++bit) {
-      const uint32_t clr = (uint32_t)(((int32_t)(nd << (31 - bit))) >> 31);  // ~0 where the bit is 0
-      const uint64_t bal = __ballot(clr == 0u);
-      mlo &= (uint32_t)bal ^ clr;
-      mhi &= (uint32_t)(bal >> 32) ^ clr;
+      const uint32_t c0 = (uint32_t)(((int32_t)(nd0 << (31 - bit))) >> 31);  // ~0 where the bit is 0
+      const uint32_t c1 = (uint32_t)(((int32_t)(nd1 << (31 - bit))) >> 31);
+      const uint64_t b0 = __ballot(c0 == 0u), b1 = __ballot(c1 == 0u);
+      m0lo &= (uint32_t)b0 ^ c0;
+      m0hi &= (uint32_t)(b0 >> 32) ^ c0;
+      m1lo &= (uint32_t)b1 ^ c1;
+      m1hi &= (uint32_t)(b1 >> 32) ^ c1;
     }
-    const uint32_t below = __builtin_amdgcn_mbcnt_hi(mhi, __builtin_amdgcn_mbcnt_lo(mlo, 0u));
-    uint32_t pre = 0;
-    if (valid && below == 0)
-      pre = atomicAdd(&S.wcnt[w][d], (uint32_t)(__popc(mlo) + __popc(mhi)));
-    // lowest lane of the group, and this lane's place after it
-    const uint32_t lead = mlo ? (uint32_t)__builtin_ctz(mlo) : 32u + (uint32_t)__builtin_ctz(mhi | 0x80000000u);
-    rank[it] = pre;
-    dg[it] |= (lead << 16) | (below << 24);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const uint32_t mlo = q ? m1lo : m0lo, mhi = q ? m1hi : m0hi, d = q ? d1 : d0;
+      const bool valid = q ? v1 : v0;
+      const uint32_t below = __builtin_amdgcn_mbcnt_hi(mhi, __builtin_amdgcn_mbcnt_lo(mlo, 0u));
+      uint32_t pre = 0;
+      if (valid && below == 0)
+        pre = atomicAdd(&S.wcnt[w][d], (uint32_t)(__popc(mlo) + __popc(mhi)));
+      // lowest lane of the group, and this lane's place after it
+      const uint32_t lead =
+          mlo ? (uint32_t)__builtin_ctz(mlo) : 32u + (uint32_t)__builtin_ctz(mhi | 0x80000000u);
+      rank[it + q] = pre;
+      dg[it + q] = d | (lead << 16) | (below << 24);
+    }
   }
 #pragma unroll
   for (int it = 0; it < C::SI; ++it) {
