@@ -1296,13 +1296,14 @@ __device__ __forceinline__ void write_pend(const Ws& ws, int t, int b, int j, co
 // gets the carry-out parts of the tiles it covers, summed in a fixed order.
 template <class C>
 __device__ void fix_tile(const Ws& ws, const GIo& io, int t, int key_mode, uint32_t want,
-                         int64_t N) {
+                         int64_t N, const BlockCtl& bc) {
   const int lane = threadIdx.x & 63;
   const Pend pd = ws.pend[t];
   if (!pd.valid) return;
   const int b = (int)pd.b, j = (int)pd.j;
-  const FrameDesc fd = ws.fd[b];
-  const FrameParams f = frame_params(ws, b, key_mode, C::W);
+  // one-phase launches hold every frame's descriptor and grid in LDS
+  const FrameDesc fd = bc.cached ? bc.fda[b] : ws.fd[b];
+  const FrameParams f = bc.cached ? bc.fpa[b] : frame_params(ws, b, key_mode, C::W);
   const int fb = f.passes & 1;
   const uint32_t* klo = ws.lo[fb] + fd.off;
   const uint32_t* khi = ws.hi[fb] + fd.off;
@@ -2081,7 +2082,7 @@ __global__ __launch_bounds__(C::BLOCK, (kMinWaves<C, KIND>)) void vg_pipeline_ke
     } else if (ph == C::PH_FIX) {
       if constexpr (KIND == kAll || KIND == kFix) {
         const int tf = t * C::NW + (int)(threadIdx.x >> 6);
-        if (tf < hdr.NTr) fix_tile<C>(ws, io, tf, hdr.key_mode, hdr.want, hdr.N);
+        if (tf < hdr.NTr) fix_tile<C>(ws, io, tf, hdr.key_mode, hdr.want, hdr.N, bc);
       }
     } else {
       const FrameParams f = *fpp;
