@@ -958,7 +958,7 @@ __device__ void stream_big_tiles(const Ws& ws, const GIo& io, const CallHdr& hdr
 template <class C>
 __device__ void sort_tile(const Ws& ws, const GIo& io, typename C::SortSmem& S, const FrameDesc& fd,
                           int b, int j, int p, const FrameParams& f, int key_mode,
-                          bool persistent, uint32_t* claim, bool& have_pre, uint32_t& pre) {
+                          bool persistent) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int Rb = 1 << f.w;
   const uint32_t mask = (uint32_t)Rb - 1u;
@@ -1151,10 +1151,6 @@ __device__ void sort_tile(const Ws& ws, const GIo& io, typename C::SortSmem& S, 
     S.gbase[d] = dex + excl - tex;
   }
   __syncthreads();
-  if (claim != nullptr && threadIdx.x == 0) {
-    pre = atomicAdd(claim, 1u);
-    have_pre = true;
-  }
 
   // write runs of equal digits to their global places
   const int dst = (p + 1) & 1;
@@ -1685,16 +1681,12 @@ __device__ __forceinline__ int wave_search(const uint32_t* a, int n, uint32_t v)
 template <class C>
 __device__ __forceinline__ void next_item(const Ws& ws, const CallHdr& hdr, BlockCtl& bc,
                                        uint32_t* counter, bool persistent, bool multi, int ph_lo,
-                                       uint32_t total, bool stat, uint32_t& sitem, bool& have_pre,
-                                       uint32_t pre) {
+                                       uint32_t total, bool stat, uint32_t& sitem) {
   for (;;) {
     uint32_t item;
     if (stat) {  // tiles that wait on no tile: a fixed order
       item = sitem;
       sitem += gridDim.x;
-    } else if (have_pre) {  // claimed during the previous tile
-      item = pre;
-      have_pre = false;
     } else {
       item = atomicAdd(counter, 1u);
     }
@@ -2003,19 +1995,13 @@ __global__ __launch_bounds__(C::BLOCK, (kMinWaves<C, KIND>)) void vg_pipeline_ke
   // One-phase radix (in their own order), reduce and fix-up launches with
   // every frame's tables in LDS take the fast dispatch: thread 0 only takes
   // the ticket, and every wave decodes it by itself, so a tile starts one
-  // barrier after its ticket.  Radix tiles there claim their next ticket once
-  // past their look-back (only the scatter is left, which waits on no tile),
-  // so the claim's latency overlaps the scatter.  Other launches go through
-  // next_item on thread 0.
+  // barrier after its ticket.  Other launches go through next_item on thread 0.
   const bool fast = cache && !persistent && !multi &&
                     (KIND == kSort ? own_order : (KIND == kRed || KIND == kFix));
   // fix-up tiles only read what the reduce launch wrote: workgroup g takes
   // items g, g + G, ... instead of queue tickets
   const bool stat = !persistent && KIND == kFix;
   uint32_t sitem = blockIdx.x;
-  uint32_t* const claim = fast && KIND == kSort ? counter : nullptr;
-  bool have_pre = false;
-  uint32_t pre = 0;
   for (;;) {
     if (threadIdx.x == 0) {
       if (fast) {
@@ -2023,16 +2009,12 @@ __global__ __launch_bounds__(C::BLOCK, (kMinWaves<C, KIND>)) void vg_pipeline_ke
         if (stat) {
           item = sitem;
           sitem += gridDim.x;
-        } else if (have_pre) {
-          item = pre;
-          have_pre = false;
         } else {
           item = atomicAdd(counter, 1u);
         }
         bc.item = item;
       } else {
-        next_item<C>(ws, hdr, bc, counter, persistent, multi, ph_lo, total, stat, sitem, have_pre,
-                     pre);
+        next_item<C>(ws, hdr, bc, counter, persistent, multi, ph_lo, total, stat, sitem);
       }
     }
     __syncthreads();
@@ -2091,8 +2073,7 @@ __global__ __launch_bounds__(C::BLOCK, (kMinWaves<C, KIND>)) void vg_pipeline_ke
           hist_tile<C>(ws, io, sm.hist, fd, b, j, f, hdr.key_mode, hdr.want, persistent);
       } else if (ph < C::PH_RED) {
         if constexpr (KIND == kAll || KIND == kSort)
-          sort_tile<C>(ws, io, sm.sort, fd, b, j, ph - C::PH_SORT0, f, hdr.key_mode, multi, claim,
-                       have_pre, pre);
+          sort_tile<C>(ws, io, sm.sort, fd, b, j, ph - C::PH_SORT0, f, hdr.key_mode, multi);
       } else {
         if constexpr (KIND == kAll || KIND == kRed) {
           const int dt = fast ? (int)bc.vt0[b] + j : fd.tr0 + j;
