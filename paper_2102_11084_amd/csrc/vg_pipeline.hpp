@@ -148,7 +148,7 @@ __device__ __forceinline__ void block_excl_scan2(uint32_t va, uint32_t vb, uint3
 
 // Decoupled look-back: sum the published values of tiles k0, k0-1, ... down
 // to the first inclusive prefix.  LB descriptors are read per round trip.
-constexpr int kLookBatchSort = 4;   // per digit, per round trip
+constexpr int kLookBatchSort = 2;   // per digit, per round trip
 
 __device__ __forceinline__ uint32_t look_back32(const uint32_t* desc, size_t stride, int k0,
                                                 int lo, Ctl* ctl) {
