@@ -118,6 +118,38 @@ def test_graph_replay_matches_eager():
     eager.close()
 
 
+@pytest.mark.parametrize("mode", [vg.EXEC_PHASED, vg.EXEC_PERSISTENT])
+def test_timed_launches_match_graph_replay(mode):
+    """Per-launch event timing (launches outside the graph) gives the same
+    bytes as graph replay, and names every launch of the call in order."""
+    print(f"case timed launches, exec mode {mode}", flush=True)
+    x, y, z, rgb, offs, leaves = small_batch(seed=6)
+    t = vg.default_tuning(exec_mode=mode)
+    plan = vg.BatchPlan(16, 400_000, vg.KEY_LINEAR, t, use_graph=True)
+    gg = run_batched(x, y, z, rgb, offs, leaves, plan=plan)
+    plan.set_timing(True)
+    gt = run_batched(x, y, z, rgb, offs, leaves, plan=plan)
+    times = plan.kernel_times()
+    plan.set_timing(False)
+    plan.close()
+    n = int(gg["out_offsets"][-1])
+    for k in gg:
+        if k == "m":
+            continue
+        full = k in ("point_cell", "out_offsets", "frame_status")
+        a, b = (gg[k], gt[k]) if full else (gg[k][:n], gt[k][:n])
+        assert np.array_equal(np.ascontiguousarray(a).view(np.uint8),
+                              np.ascontiguousarray(b).view(np.uint8)), k
+    kinds = [k for k, _ in times]
+    assert all(ms > 0.0 for _, ms in times)
+    if mode == vg.EXEC_PHASED:
+        assert kinds[0] == "init" and kinds[1:3] == ["bbox", "hist"]
+        assert kinds[-2:] == ["reduce", "fixup"]
+        assert set(kinds[3:-2]) == {"sort"} and len(kinds[3:-2]) >= 1
+    else:
+        assert kinds == ["init", "pipeline"]
+
+
 def test_batch_of_one_equals_plain():
     x, y, z, rgb = dg.frame_640x480()
     offs = np.array([0, x.size], np.int64)
