@@ -1297,49 +1297,31 @@ __device__ void fix_tile(const Ws& ws, const GIo& io, int t, int key_mode, uint3
   const Pend pd = ws.pend[t];
   if (!pd.valid) return;
   const int b = (int)pd.b, j = (int)pd.j;
-  // one-phase launches hold every frame's descriptor and grid in LDS
+  // one-phase launches hold every frame's descriptors in LDS
   const FrameDesc fd = bc.cached ? bc.fda[b] : ws.fd[b];
-  const FrameParams f = bc.cached ? bc.fpa[b] : frame_params(ws, b, key_mode, C::W);
-  const int fb = f.passes & 1;
-  const uint32_t* klo = ws.lo[fb] + fd.off;
-  const uint32_t* khi = ws.hi[fb] + fd.off;
-  const uint32_t* kid = ws.idx[fb] + fd.off;
-  // where the cell starts: the previous tile knows if the head is there, else
-  // search the frame's sorted keys backwards (galloping, then bisection)
+  // where the cell starts: at the last head of the nearest earlier tile that
+  // has one (the tiles in between hold only points of this cell, and their
+  // carry-outs say so); the wave reads 64 earlier carry-outs at a time
   uint32_t start = 0, ref = 0;
-  if (lane == 0) {
-    const Frag pf = ws.frag[t - 1];
-    if (pf.head_pos != kNoHead) {
-      start = pf.head_pos;
-      ref = pf.ref;
-    } else {
-      const uint64_t key = ((uint64_t)pd.hi << 32) | pd.lo;
-      uint32_t hi = (uint32_t)((j - 1) * C::TR);  // the cell covers all of tile j-1
-      uint32_t step = (uint32_t)C::TR;
-      uint32_t lo = 0;
-      for (;;) {  // find lo <= start <= hi
-        if (hi <= step) break;
-        const uint32_t probe = hi - step;
-        const uint64_t kp = ((uint64_t)(f.wide ? khi[probe] : 0u) << 32) | klo[probe];
-        if (kp < key) {
-          lo = probe + 1;
-          break;
-        }
-        hi = probe;
-        step *= 2;
-      }
-      while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        const uint64_t km = ((uint64_t)(f.wide ? khi[mid] : 0u) << 32) | klo[mid];
-        if (km < key) lo = mid + 1;
-        else hi = mid;
-      }
-      start = lo;
-      ref = kid[start];
+  for (int k0 = t - 1;; k0 -= 64) {
+    const int k = k0 - lane;
+    uint32_t hp = kNoHead, rf = 0;
+    if (k >= fd.tr0) {
+      hp = ws.frag[k].head_pos;
+      rf = ws.frag[k].ref;
+    }
+    const uint64_t found = __ballot(hp != kNoHead);
+    if (found) {
+      const int src = __ffsll((unsigned long long)found) - 1;
+      start = __shfl(hp, src);
+      ref = __shfl(rf, src);
+      break;
+    }
+    if (k0 - 64 < fd.tr0) {  // the frame's first tile always holds a head
+      if (lane == 0) atomicOr(&ws.ctl->error, 1u);
+      return;
     }
   }
-  start = __shfl(start, 0);
-  ref = __shfl(ref, 0);
   const int th = (int)(start / (uint32_t)C::TR);
   const int nf = j - th;
   const int tbase = fd.tr0 + th;
