@@ -418,7 +418,102 @@ def pin_backward_fd(lib, seed=6):
         assert abs(fd - grad[i, a]) <= 1e-7 * max(1.0, abs(fd)), (i, a, fd, grad[i, a])
 
 
+def pin_centroids_fixed(lib, seed=8):
+    """Values of the fixed-assignment centroid map: per cell, the exact mean
+    (math.fsum) of the points assigned to it; empty cells give 0, and rows
+    outside [0, m) are ignored.  Its derivative alone is pinned by the
+    finite-difference pin; this pins the values themselves."""
+    rng = np.random.default_rng(seed)
+    for trial in range(20):
+        n = int(rng.integers(0, 400))
+        m = int(rng.integers(1, 40))
+        P = rng.normal(0, 10, size=(n, 3)) * 10.0 ** rng.integers(-3, 4)
+        pc = rng.integers(-2, m + 2, size=n).astype(np.int32)  # some rows outside [0, m)
+        cx, cy, cz = oracle.centroids_fixed(P[:, 0], P[:, 1], P[:, 2], pc, m, lib=lib)
+        got = np.stack([cx, cy, cz], 1)
+        for c in range(m):
+            mem = np.flatnonzero(pc == c)
+            for a in range(3):
+                exp = math.fsum(P[mem, a]) / mem.size if mem.size else 0.0
+                assert abs(got[c, a] - exp) <= 1e-12 * max(1.0, abs(exp)), (trial, c, a)
+    # the centroids of the filter's own assignment are its centroids
+    x, y, z = (rng.uniform(-2, 2, 500).astype(np.float32) for _ in range(3))
+    r = oracle.downsample(x, y, z, None, 0.5, lib=lib)
+    cx, cy, cz = oracle.centroids_fixed(x, y, z, r["point_cell"], r["m"], lib=lib)
+    for got, name in ((cx, "cx"), (cy, "cy"), (cz, "cz")):
+        assert np.allclose(got, r[name], rtol=1e-12, atol=1e-12)
+
+
+def _frames_for_batch(rng):
+    """Uneven frames for the batched form: adversarial clouds with leaves that
+    differ per frame, an empty frame, an all-NaN frame, an overflowing frame."""
+    frames, leaves, expect = [], [], []
+    for leaf in (0.05, 1.0, 0.37, 0.1, 0.5):
+        n = int(rng.integers(5, 60))
+        p = _adversarial_cloud(rng, n, leaf)
+        p = np.where(np.abs(p) > 1e4, p - np.float32(1e5), p).astype(np.float32)
+        frames.append(p)
+        leaves.append(leaf)
+        expect.append(oracle.OK)
+    frames.insert(1, np.zeros((0, 3), np.float32))
+    leaves.insert(1, 0.2)
+    expect.insert(1, oracle.OK)
+    frames.insert(3, np.full((7, 3), np.nan, np.float32))
+    leaves.insert(3, 0.2)
+    expect.insert(3, oracle.OK)
+    ov = np.array([[0.0, 0.0, 0.0], [1e4, 1.0, 1.0], [5.0, 0.5, 0.5]], np.float32)
+    frames.insert(5, ov)
+    leaves.insert(5, 1e-3)
+    expect.insert(5, oracle.ERR_GRID_OVERFLOW)
+    return frames, leaves, expect
+
+
+def pin_batched(lib, seed=9, batched=None):
+    """The batched form against brute-force grouping of every frame with its
+    own leaf (its own box, frame-local indices), an overflowing frame reported
+    in its status with no cells, and a bad leaf raised, not reported."""
+    batched = batched or oracle.downsample_batched
+    rng = np.random.default_rng(seed)
+    frames, leaves, expect = _frames_for_batch(rng)
+    offs = np.zeros(len(frames) + 1, np.int64)
+    offs[1:] = np.cumsum([f.shape[0] for f in frames])
+    P = np.concatenate(frames)
+    rgb = rng.integers(0, 256, size=(P.shape[0], 3), dtype=np.uint8)
+    x, y, z = P[:, 0].copy(), P[:, 1].copy(), P[:, 2].copy()
+    res, status = batched(x, y, z, rgb, offs, np.array(leaves, np.float32), lib=lib)
+    assert list(status) == expect and len(res) == len(frames)
+    for b, (r, s) in enumerate(zip(res, status)):
+        s0, s1 = int(offs[b]), int(offs[b + 1])
+        if s != oracle.OK:
+            assert r is None
+            continue
+        if not np.isfinite(P[s0:s1]).all(1).any():
+            assert r["m"] == 0 and (r["point_cell"] == -1).all() and r["point_cell"].size == s1 - s0
+            continue
+        groups = _brute(x[s0:s1], y[s0:s1], z[s0:s1], rgb[s0:s1], leaves[b])
+        assert r["m"] == len(groups), b
+        assert r["point_cell"].size == s1 - s0
+        for c, (t, mem) in enumerate(groups):
+            mem = np.array(mem)
+            assert r["count"][c] == mem.size and r["ref_index"][c] == mem.min(), (b, c)
+            assert (r["point_cell"][mem] == c).all()
+            for a, name in enumerate(("cx", "cy", "cz")):
+                exp = math.fsum(float(v) for v in P[s0 + mem, a]) / mem.size
+                assert abs(r[name][c] - exp) <= 1e-12 * max(1.0, abs(exp)), (b, c, a)
+            for a in range(3):
+                tot = int(rgb[s0 + mem, a].astype(np.int64).sum())
+                assert r["rgb"][c, a] == (tot + mem.size // 2) // mem.size
+    bad = np.array(leaves, np.float32)
+    bad[2] = 0.0
+    try:
+        batched(x, y, z, rgb, offs, bad, lib=lib)
+    except oracle.OracleError as err:
+        assert err.status == oracle.ERR_LEAF
+    else:
+        raise AssertionError("a bad leaf must raise, not be reported as a frame status")
+
+
 ALL_PINS = [pin_dyadic, pin_brute_force, pin_single_cell, pin_symmetric_pairs, pin_leaf_to_zero,
             pin_invariants, pin_permutation_duplication, pin_colour_rounding,
             pin_invalid_and_errors, pin_overflow_boundary, pin_denormals, pin_golden,
-            pin_backward_fd]
+            pin_backward_fd, pin_centroids_fixed, pin_batched]

@@ -32,6 +32,10 @@ MUTANTS = {
     "point_cell_off": ("point_cell[i] = (int32_t)cells.find(keys[i])->second.rank;",
                        "point_cell[i] = (int32_t)cells.find(keys[i])->second.rank + 1;"),
     "mean_divides_n_plus_1": ("if (cx) cx[r] = c.sum[0] / nn;", "if (cx) cx[r] = c.sum[0] / (nn + 1);"),
+    "fixed_sum_transposed": ("s[3 * c + 1] += y[i];", "s[3 * c + 1] += z[i];"),
+    "fixed_constant_offset": ("cx[k] = cnt[k] ? s[3 * k + 0] / nn : 0.0;",
+                              "cx[k] = cnt[k] ? s[3 * k + 0] / nn + 1e-3 : 0.0;"),
+    "fixed_drops_row_0": ("if (c < 0 || c >= m) continue;", "if (c <= 0 || c >= m) continue;"),
 }
 
 
@@ -50,3 +54,28 @@ def test_mutant_is_caught(name, tmp_path):
         except Exception as err:  # any failure of a pin counts as catching the mutant
             caught.append((pin.__name__, type(err).__name__))
     assert caught, f"mutant {name} passed every pin"
+
+
+# Slips in the batched form (oracle/__init__.py), planted in a copy of the
+# function's source and passed to the batched pin in place of the original.
+BATCHED_MUTANTS = {
+    "next_frame_leaf": ("leaves[b],", "leaves[min(b + 1, len(leaves) - 1)],"),
+    "slice_off_by_one": ("s, e = int(frame_offsets[b]), int(frame_offsets[b + 1])",
+                         "s, e = int(frame_offsets[b]), int(frame_offsets[b + 1]) - (b % 2)"),
+    "swallows_errors": ("if err.status != ERR_GRID_OVERFLOW:\n                raise", "if False:\n                raise"),
+    "axes_swapped": ("downsample(x[s:e], y[s:e], z[s:e]", "downsample(x[s:e], z[s:e], y[s:e]"),
+    "status_ok_on_overflow": ("status.append(err.status)", "status.append(OK)"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(BATCHED_MUTANTS))
+def test_batched_mutant_is_caught(name):
+    import inspect
+    import textwrap
+    src = textwrap.dedent(inspect.getsource(oracle.downsample_batched))
+    old, new = BATCHED_MUTANTS[name]
+    assert src.count(old) == 1, f"mutation anchor not unique/found: {name}"
+    ns = dict(vars(oracle))
+    exec(compile(src.replace(old, new), "<mutant>", "exec"), ns)
+    with pytest.raises(Exception):
+        pins.pin_batched(oracle.load(), batched=ns["downsample_batched"])
