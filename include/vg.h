@@ -117,31 +117,47 @@ typedef struct vg_options {
   const vg_tuning *tuning;
 } vg_options;
 
-/* Human-readable name of a status; never NULL. */
+/* Human-readable name of a status; never NULL.  (Library helper; not in the
+ * paper.) */
 const char *vg_status_string(vg_status s);
 
-/* Fills *t with the built-in default tuning.  VG_ERR_ARG if t is NULL. */
+/* Fills *t with the built-in default tuning.  VG_ERR_ARG if t is NULL.
+ * (The paper sizes its launch by the device's processor count, Sec. II-C
+ * after Alg. 1; the tuning generalises that choice.) */
 vg_status vg_default_tuning(vg_tuning *t);
 
-/* VG_OK if the library holds kernels for this tuning, else VG_ERR_ARG. */
+/* VG_OK if the library holds kernels for this tuning, else VG_ERR_ARG.
+ * (Library helper; not in the paper.) */
 vg_status vg_tuning_supported(const vg_tuning *t);
 
 /* Device workspace needed for n_total points in n_frames frames (0 on bad
- * arguments).  Grows linearly in n_total (about 42 bytes per point). */
+ * arguments).  Grows linearly in n_total (about 42 bytes per point): the
+ * sorted key/value table of Sec. II-C (double-buffered key and index words)
+ * and the per-tile look-back state. */
 size_t vg_workspace_bytes(int64_t n_total, int n_frames, const vg_tuning *t);
 
 /* Downsample one cloud on the default stream with an internal workspace.
+ * The operation of steps 1-6 above: Sec. II-C (grid over space, per-point
+ * subdivision lookup, radix-sorted subdivision table, per-subdivision counts)
+ * and Alg. 1 (lookup, table update, radix sort, deletion of the merged points,
+ * copy of the filtered cloud back to the caller), with the centroid rule of
+ * the voxel filter named in Sec. I and Sec. II-C.
  * p: device points; n: number of points, 0 <= n < 2^30; leaf: cell edge;
  * out: device outputs of capacity n; m: host, receives the number of cells.
- * Synchronous: returns after the cells are written (one stream sync). */
+ * Synchronous: returns after the cells are written (one stream sync).
+ * Errors: VG_ERR_ARG / VG_ERR_LEAF before any launch; VG_ERR_GRID_OVERFLOW
+ * and VG_ERR_DEVICE after the sync. */
 vg_status vg_downsample(const vg_points *p, int64_t n, float leaf, vg_cells *out, int64_t *m);
 
-/* As vg_downsample, with a stream, a caller workspace, key mode and tuning.
- * Waits for the stream only to read m back. */
+/* As vg_downsample (Sec. II-C, Alg. 1), with a stream, a caller workspace,
+ * key mode and tuning.  Waits for the stream only to read m back; on an error
+ * after work was enqueued it also waits for that work before returning, so
+ * the workspace and the library's staging buffer are free again. */
 vg_status vg_downsample_ex(const vg_points *p, int64_t n, float leaf, vg_cells *out, int64_t *m,
                            const vg_options *o);
 
-/* Backward of the centroids with the cell assignment held fixed:
+/* Not in the paper (a differentiable form of the filter): backward of the
+ * centroids with the cell assignment held fixed:
  *   d{x,y,z}[i] = g{x,y,z}[c] / count[c] for c = point_cell[i] >= 0, else 0.
  * g*, count: device [m]; point_cell: device [n] (as written by a forward
  * call); d*: device [n].  Asynchronous on `stream`.  0 <= n < 2^31. */
@@ -152,24 +168,33 @@ vg_status vg_downsample_backward(const float *gx, const float *gy, const float *
 /* ---- batched form: many frames of uneven size and leaf in one launch ---- */
 typedef struct vg_batch_plan vg_batch_plan;
 
-/* Plan for up to max_frames frames and max_total_points points in total
+/* Not in the paper (which filters one camera frame per call, Alg. 1): a plan
+ * for batches of up to max_frames frames and max_total_points points in total
  * (< 2^31, and < 2^30 per frame).  Allocates the device workspace and a
- * pinned descriptor buffer.  tuning NULL = default. */
+ * pinned descriptor buffer.  tuning NULL = default.  The paper's processor-
+ * count launch sizing (Sec. II-C after Alg. 1) becomes the plan's fixed grids. */
 vg_status vg_batch_plan_create(int max_frames, int64_t max_total_points, vg_key_mode key_mode,
                                const vg_tuning *tuning, vg_batch_plan **plan);
 
-/* If use_graph != 0, the plan records its launch sequence (descriptor copy,
- * state reset, pipeline kernel) into a hipGraph on first use and replays it. */
+/* Not in the paper: if use_graph != 0, the plan records its launch sequence
+ * (descriptor copy, state reset, pipeline kernels, status kernel) into a
+ * hipGraph on first use and replays it. */
 vg_status vg_batch_plan_set_graph(vg_batch_plan *plan, int use_graph);
 
-/* Downsample B frames concatenated in p.  frame_offsets: host [B+1],
+/* Not in the paper (batching of frames); every frame is filtered exactly as
+ * vg_downsample filters it (Sec. II-C, Alg. 1), with its own box and leaf.
+ * Downsample B frames concatenated in p.  frame_offsets: host [B+1],
  * non-decreasing, frame b = points [frame_offsets[b], frame_offsets[b+1]).
  * leaf: host [B].  out: device, capacity frame_offsets[B]; frame b's cells
  * are rows [out_offsets[b], out_offsets[b+1]) of every output array.
- * out_offsets: device int64 [B+1]; frame_status: device int32 [B]
- * (VG_OK or VG_ERR_GRID_OVERFLOW; an overflowing frame has no rows).
+ * out_offsets: device int64 [B+1]; frame_status: device int32 [B]:
+ *   VG_OK, VG_ERR_GRID_OVERFLOW (that frame has no rows), or VG_ERR_DEVICE in
+ *   every frame when a device-side wait of the call timed out (then every
+ *   output of the call, out_offsets included, is unspecified).
  * Fully asynchronous on `stream`; a later call on the same plan waits for
- * the earlier one's descriptor copy before reusing the pinned buffer. */
+ * the earlier one's descriptor copy before reusing the pinned buffer.
+ * Host-side errors (VG_ERR_ARG, VG_ERR_LEAF) are returned before anything is
+ * enqueued. */
 vg_status vg_downsample_batched(vg_batch_plan *plan, const vg_points *p,
                                 const int64_t *frame_offsets, const float *leaf, int B,
                                 vg_cells *out, int64_t *out_offsets, int32_t *frame_status,
@@ -186,7 +211,8 @@ typedef enum vg_kernel_kind {
   VG_KERNEL_PIPELINE = 6  /* every phase in one persistent launch */
 } vg_kernel_kind;
 
-/* Per-launch timing.  With enable != 0 every later vg_downsample_batched call
+/* Measurement support (not in the paper, which times whole filter calls, Table
+ * I): per-launch timing.  With enable != 0 every later vg_downsample_batched call
  * on this plan launches its kernels directly (not through the plan's graph)
  * and records a HIP event pair on the call's stream around each launch.
  * Waits for the plan's outstanding work before switching. */
@@ -199,6 +225,13 @@ vg_status vg_batch_plan_set_timing(vg_batch_plan *plan, int enable);
  * VG_ERR_ARG if timing is off. */
 vg_status vg_batch_plan_kernel_times(vg_batch_plan *plan, int *kinds, float *ms, int cap,
                                      int *count);
+
+/* Test support for callers' error handling (not in the paper): while enable
+ * != 0, each later call on the plan starts with the device-side time-out flag
+ * raised, as a bounded wait that timed out would raise it.  Every kernel then
+ * exits without touching the outputs and every frame_status reads
+ * VG_ERR_DEVICE.  Nothing waits or faults. */
+vg_status vg_batch_plan_set_fail_waits(vg_batch_plan *plan, int enable);
 
 /* Releases the plan (waits for its work to finish first). */
 vg_status vg_batch_plan_destroy(vg_batch_plan *plan);

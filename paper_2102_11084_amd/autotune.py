@@ -2,8 +2,11 @@
 digit width, launch form and workgroups per CU for a workload.
 
 Every candidate built into the library is run on the workload (seeded
-synthetic RGB-D frames, see datagen.batch); its cell keys, counts and rows
-must equal the first candidate's bit for bit, else it is rejected.  The
+synthetic RGB-D frames, see datagen.batch); its cell keys, counts, centroids,
+colours and rows must equal the first good candidate's bit for bit, its
+centroids must agree with that candidate's within twice the parity tolerance
+(1e-6 of the leaf plus one ulp), and no frame may report a failure, else it is
+rejected.  The
 fastest candidate (median of timed runs, HIP events on the stream) is written
 as JSON, which bench.py and vg.load_tuning read.
 
@@ -60,7 +63,7 @@ def main(argv=None):
     d = [torch.from_numpy(a).to(dev) for a in (x, y, z, rgb.reshape(-1))]
     outputs = ("xyz", "rgb", "count", "key")
     stream = torch.cuda.current_stream(dev)
-    ref = None
+    ref = ref_xyz = row_leaf = None
     results = []
     for t in candidates(vg):
         plan = vg.BatchPlan(len(leaves), N, vg.KEY_LINEAR, t, use_graph=True)
@@ -69,13 +72,22 @@ def main(argv=None):
             plan.run(*d, offs, leaves, out=outs)
         torch.cuda.synchronize()
         m = int(outs[0]["out_offsets"][-1].item())
-        sig = (outs[0]["key"][:m].cpu().numpy().tobytes(), outs[0]["count"][:m].cpu().numpy().tobytes(),
-               outs[0]["out_offsets"].cpu().numpy().tobytes())
-        ok = True
-        if ref is None:
+        # keys, counts, colours and rows bit for bit; centroids within twice
+        # the parity tolerance of each other (tile sizes change where the
+        # compensated sums are split); no frame may report a failure
+        sig = tuple(outs[0][k][:m].cpu().numpy().tobytes() for k in ("key", "count", "rgb"))
+        sig += (outs[0]["out_offsets"].cpu().numpy().tobytes(),)
+        xyz = np.stack([outs[0][k][:m].cpu().numpy() for k in ("x", "y", "z")], 1)
+        ok = bool((outs[0]["frame_status"].cpu().numpy() == 0).all())
+        if ref is None and ok:
             ref = sig
+            ref_xyz = xyz.astype(np.float64)
+            row_leaf = np.repeat(leaves.astype(np.float64), np.diff(outs[0]["out_offsets"].cpu().numpy()))
         elif sig != ref:
             ok = False
+        else:
+            ulp = np.spacing(np.abs(ref_xyz).astype(np.float32)).astype(np.float64)
+            ok = ok and bool((np.abs(xyz - ref_xyz) <= 2 * (1e-6 * row_leaf[:, None] + ulp)).all())
         times = []
         for _ in range(args.reps):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -231,13 +231,14 @@ bool cells_consistent(const vg_cells* c) {
 bool fill_staging(char* st, const Layout& L, const Variant& v, const vg_points* p,
                   const int64_t* offs, const float* leaves, const float* invs, int B,
                   const vg_cells* out, int64_t* out_offsets, int32_t* frame_status, int key_mode,
-                  CallHdr* hdr_out) {
+                  int fail_waits, CallHdr* hdr_out) {
   CallHdr hdr;
   std::memset(&hdr, 0, sizeof hdr);
   hdr.B = B;
   hdr.key_mode = key_mode;
   hdr.N = offs[B] - offs[0];
   hdr.want = want_mask(out);
+  hdr.fail_waits = fail_waits;
   if (!p->rgb) hdr.want &= ~(uint32_t)kOutRGB;
   Io io;
   std::memset(&io, 0, sizeof io);
@@ -385,6 +386,7 @@ vg_status enqueue(const Variant& v, const Layout& L, const Ws& ws, const char* s
       ph = hi;
     }
   }
+  hipLaunchKernelGGL(vg_status_kernel, dim3(1), dim3(256), 0, s, ws);
   if (hipGetLastError() != hipSuccess) return VG_ERR_DEVICE;
   return VG_OK;
 }
@@ -485,10 +487,12 @@ vg_status vg_downsample_ex(const vg_points* p, int64_t n, float leaf, vg_cells* 
   int64_t* d_off = reinterpret_cast<int64_t*>(static_cast<char*>(base) + L.outoff);
   int32_t* d_st = reinterpret_cast<int32_t*>(static_cast<char*>(base) + L.fstat);
   vg_status rc = VG_OK;
-  if (!fill_staging(st, L, *v, p, offs, &leaf, &inv, 1, out, d_off, d_st, o->key_mode, &hdr)) {
+  bool enqueued = false;
+  if (!fill_staging(st, L, *v, p, offs, &leaf, &inv, 1, out, d_off, d_st, o->key_mode, 0, &hdr)) {
     rc = VG_ERR_ARG;
   } else {
     const int mode = o->tuning ? o->tuning->exec_mode : kDefaultTuning.exec_mode;
+    enqueued = true;
     rc = enqueue(*v, L, ws, st, mode, cus, bpc, s);
   }
   Readback* rb = reinterpret_cast<Readback*>(st + L.staged);
@@ -512,10 +516,11 @@ vg_status vg_downsample_ex(const vg_points* p, int64_t n, float leaf, vg_cells* 
       *m = rb->off[1] - rb->off[0];
     }
   }
-  if (owned) {
-    (void)hipStreamSynchronize(s);
-    (void)hipFree(base);
-  }
+  // On an error after something was enqueued, the staged copy may still be
+  // reading this thread's pinned buffer, and the kernels the workspace: wait
+  // before either can be reused.
+  if (owned || (enqueued && rc != VG_OK)) (void)hipStreamSynchronize(s);
+  if (owned) (void)hipFree(base);
   return rc;
 }
 
@@ -563,6 +568,7 @@ struct vg_batch_plan {
   hipGraph_t graph;
   hipGraphExec_t gexec;
   LaunchTimer* timer;  // non-null while timing is on
+  int fail_waits;      // test support: calls start with the time-out flag raised
 };
 
 extern "C" {
@@ -593,6 +599,7 @@ vg_status vg_batch_plan_create(int max_frames, int64_t max_total_points, vg_key_
   P->gexec = nullptr;
   P->done = nullptr;
   P->timer = nullptr;
+  P->fail_waits = 0;
   vg_status rc = VG_OK;
   if (hipGetDevice(&P->device) != hipSuccess) rc = VG_ERR_DEVICE;
   if (rc == VG_OK && (P->cus = device_cus(P->device)) <= 0) rc = VG_ERR_DEVICE;
@@ -618,6 +625,12 @@ vg_status vg_batch_plan_create(int max_frames, int64_t max_total_points, vg_key_
 vg_status vg_batch_plan_set_graph(vg_batch_plan* plan, int use_graph) {
   if (!plan) return VG_ERR_ARG;
   plan->use_graph = use_graph ? 1 : 0;
+  return VG_OK;
+}
+
+vg_status vg_batch_plan_set_fail_waits(vg_batch_plan* plan, int enable) {
+  if (!plan) return VG_ERR_ARG;
+  plan->fail_waits = enable ? 1 : 0;
   return VG_OK;
 }
 
@@ -685,7 +698,7 @@ vg_status vg_downsample_batched(vg_batch_plan* P, const vg_points* p, const int6
   }
   CallHdr hdr;
   if (!fill_staging(P->staging, P->L, *P->v, p, offs, leaf, P->invs, B, out, out_offsets,
-                    frame_status, P->key_mode, &hdr))
+                    frame_status, P->key_mode, P->fail_waits, &hdr))
     return VG_ERR_ARG;
   vg_status rc = VG_OK;
   if (P->use_graph && !P->timer) {

@@ -4,6 +4,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace vg {
@@ -22,7 +23,7 @@ constexpr uint64_t kFlagA64 = 1ull << 62;
 constexpr uint64_t kFlagP64 = 2ull << 62;
 constexpr uint64_t kVal64 = (1ull << 62) - 1;
 
-enum FrameStatus : int32_t { kFrameOk = 0, kFrameOverflow = 3 };
+enum FrameStatus : int32_t { kFrameOk = 0, kFrameOverflow = 3, kFrameDeviceError = 5 };
 
 // Per-call header, copied from the host.
 //   big tiles  (bbox, histogram):  NTb over all frames
@@ -35,7 +36,8 @@ struct CallHdr {
   uint32_t want;        // output mask (kOut*)
   int64_t N;            // points over all frames
   int32_t ilv_rounds;   // > 0: radix-pass tiles are taken round-robin over frames
-  int32_t pad;
+  int32_t fail_waits;   // non-zero: the call starts with the time-out flag raised (tests of
+                        // the error path: every kernel then exits without touching outputs)
 };
 
 // Round-robin order of the radix-pass tiles: round j holds tile j of every

@@ -1443,7 +1443,7 @@ __device__ void red_tile(const Ws& ws, const GIo& io, typename C::RedSmem& S, co
         st_rlx64(&ws.rdesc[dt], kFlagP64 | excl);
         if (j == 0) {
           io.out_offsets[b] = (int64_t)excl;
-          io.frame_status[b] = ld_rlx(&ws.ctl->error) ? 5 : f.status;
+          io.frame_status[b] = ld_rlx(&ws.ctl->error) ? kFrameDeviceError : f.status;
         }
         if (dt == dlast) io.out_offsets[B] = (int64_t)excl;
         if (!compact) publish_skipped<C>(ws, io, fd, j, nv, b, B, excl);
@@ -1537,7 +1537,7 @@ __device__ void red_tile(const Ws& ws, const GIo& io, typename C::RedSmem& S, co
       S.excl = excl;
       if (j == 0) {
         io.out_offsets[b] = (int64_t)excl;
-        io.frame_status[b] = ld_rlx(&ws.ctl->error) ? 5 : f.status;
+        io.frame_status[b] = ld_rlx(&ws.ctl->error) ? kFrameDeviceError : f.status;
       }
       if (dt == dlast) io.out_offsets[B] = (int64_t)(excl + H);
       if (!compact) publish_skipped<C>(ws, io, fd, j, nv, b, B, excl + H);
@@ -1824,6 +1824,9 @@ template <class C, int KIND>
 __global__ __launch_bounds__(C::BLOCK, (kMinWaves<C, KIND>)) void vg_pipeline_kernel(Ws ws, int ph_lo, int ph_hi) {
   __shared__ typename SmemOf<C, KIND>::type sm;
   __shared__ BlockCtl bc;
+  // after a device-side time-out (raised by an earlier launch of the call)
+  // nothing more runs: inputs of later phases may be incomplete
+  if (ld_rlx(&ws.ctl->error) != 0) return;
   const CallHdr hdr = *ws.hdr;
   const GIo io = global_view(*ws.io);
   const bool persistent = (ph_lo == 0 && ph_hi == C::NPH);
@@ -2087,7 +2090,9 @@ __global__ void vg_init_kernel(Ws ws) {
   const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t nth = (size_t)gridDim.x * blockDim.x;
   uint32_t* ctl = reinterpret_cast<uint32_t*>(ws.ctl);
-  for (size_t i = tid; i < sizeof(Ctl) / 4; i += nth) ctl[i] = 0u;
+  constexpr size_t kErrWord = offsetof(Ctl, error) / 4;
+  for (size_t i = tid; i < sizeof(Ctl) / 4; i += nth)
+    ctl[i] = (i == kErrWord && hdr.fail_waits) ? 1u : 0u;
   uint32_t* fs = reinterpret_cast<uint32_t*>(ws.fs);
   for (size_t i = tid; i < (size_t)hdr.B * (sizeof(FrameState) / 4); i += nth) fs[i] = 0u;
   for (size_t i = tid; i < (size_t)hdr.B * ws.slots * ws.R; i += nth) ws.hist[i] = 0u;
@@ -2111,6 +2116,16 @@ __global__ void vg_init_kernel(Ws ws) {
     }
     ws.tinfo[i] = make_uint2((uint32_t)lo, t - tp[lo]);
   }
+}
+
+// Last launch of a call: a device-side time-out anywhere in the call (a
+// bounded wait that gave up, a cell head not found) marks every frame's status,
+// whichever tile raised it and whenever.
+__global__ void vg_status_kernel(Ws ws) {
+  if (__hip_atomic_load(&ws.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) return;
+  const CallHdr hdr = *ws.hdr;
+  int32_t* st = ws.io->frame_status;
+  for (int b = threadIdx.x; b < hdr.B; b += blockDim.x) st[b] = kFrameDeviceError;
 }
 
 // dL/dp_i = G[c] / count[c], c = point_cell[i]; zero where c < 0.

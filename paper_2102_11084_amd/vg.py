@@ -59,7 +59,7 @@ _lib_handle = None
 EXPORTS = ["vg_status_string", "vg_default_tuning", "vg_tuning_supported", "vg_workspace_bytes",
            "vg_downsample", "vg_downsample_ex", "vg_downsample_backward", "vg_batch_plan_create",
            "vg_batch_plan_set_graph", "vg_downsample_batched", "vg_batch_plan_set_timing",
-           "vg_batch_plan_kernel_times", "vg_batch_plan_destroy"]
+           "vg_batch_plan_kernel_times", "vg_batch_plan_set_fail_waits", "vg_batch_plan_destroy"]
 
 # vg_kernel_kind
 KERNEL_KINDS = ("init", "bbox", "hist", "sort", "reduce", "fixup", "pipeline")
@@ -90,6 +90,7 @@ def lib():
                                             ctypes.POINTER(vg_cells), P, P, P]
         L.vg_batch_plan_set_timing.argtypes = [P, ctypes.c_int]
         L.vg_batch_plan_kernel_times.argtypes = [P, P, P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+        L.vg_batch_plan_set_fail_waits.argtypes = [P, ctypes.c_int]
         L.vg_batch_plan_destroy.argtypes = [P]
         for name in EXPORTS:
             if name != "vg_status_string" and name != "vg_workspace_bytes":
@@ -267,6 +268,12 @@ class BatchPlan:
         st = lib().vg_batch_plan_set_timing(self._h, 1 if enable else 0)
         if st != VG_OK:
             raise VGError(st, "vg_batch_plan_set_timing")
+
+    def set_fail_waits(self, enable: bool):
+        """Test support: later runs start with the device time-out flag raised."""
+        st = lib().vg_batch_plan_set_fail_waits(self._h, 1 if enable else 0)
+        if st != VG_OK:
+            raise VGError(st, "vg_batch_plan_set_fail_waits")
 
     def kernel_times(self):
         """[(kind name, ms)] of the last run's kernel launches, in launch order (waits)."""

@@ -123,5 +123,6 @@ def test_batch_plan_checks():
     assert L.vg_batch_plan_destroy(None) == vg.VG_ERR_ARG
     assert L.vg_batch_plan_set_graph(None, 1) == vg.VG_ERR_ARG
     assert L.vg_batch_plan_set_timing(None, 1) == vg.VG_ERR_ARG
+    assert L.vg_batch_plan_set_fail_waits(None, 1) == vg.VG_ERR_ARG
     cnt = ctypes.c_int(5)
     assert L.vg_batch_plan_kernel_times(None, None, None, 0, ctypes.byref(cnt)) == vg.VG_ERR_ARG

@@ -97,3 +97,16 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=300)
     assert r.returncode != 0
     assert "--gpus 1" in r.stderr
+
+
+def test_step_bytes_by_kernel_by_hand():
+    # the method's per-step bytes: 12 n (box) + 12 n + 4 n_v (keys, histograms)
+    # + 16 P n_v (radix passes) + 23 n_v + 27 m (reduce), + 8 n_v pair write
+    kb = bench.step_bytes_by_kernel([100, 50, 40], [80, 0, 40], [2, 0, 3], [10, 0, 5])
+    assert kb["bbox"] == 12 * 190
+    assert kb["hist"] == 12 * 190 + 4 * 120
+    assert kb["sort"] == 16 * (2 * 80 + 3 * 40)
+    assert kb["reduce"] == 23 * 120 + 27 * 15
+    total = sum(bench.algorithmic_bytes(n, nv, p, m) for n, nv, p, m in
+                [(100, 80, 2, 10), (50, 0, 0, 0), (40, 40, 3, 5)])
+    assert kb["pipeline"] == total

@@ -162,29 +162,60 @@ def test_batch_of_one_equals_plain():
 
 
 @pytest.mark.slow
-def test_full_uneven_batch_sampled():
-    """The 64-frame uneven batch at full size: 6 frames against the oracle,
-    invariants on every frame."""
+def test_full_uneven_batch_every_frame():
+    """The 64-frame uneven batch at full size, in the bench's launch form
+    (tuned, graph replay): every frame against the oracle, and the batched
+    rows bit-identical to 64 plain calls on the same frames."""
+    import os
     x, y, z, rgb, offs, leaves = dg.batch()
-    print(f"batch of {len(leaves)} frames, {x.size} points", flush=True)
-    g = run_batched(x, y, z, rgb, offs, leaves)
+    print(f"case full batch of {len(leaves)} frames, {x.size} points", flush=True)
+    tpath = os.path.join(os.path.dirname(vg.__file__), "tuning_gfx950.json")
+    t = vg.load_tuning(tpath) if os.path.exists(tpath) else vg.default_tuning()
+    plan = vg.BatchPlan(len(leaves), x.size, vg.KEY_LINEAR, t, use_graph=True)
+    g = run_batched(x, y, z, rgb, offs, leaves, plan=plan)
+    plan.close()
     assert (g["frame_status"] == 0).all()
     oo = g["out_offsets"]
     for b in range(len(leaves)):
         s0, s1 = int(offs[b]), int(offs[b + 1])
         lo, hi = int(oo[b]), int(oo[b + 1])
-        nv = int(np.isfinite(x[s0:s1]).sum())
-        assert int(g["count"][lo:hi].astype(np.int64).sum()) == nv
-        k = g["key"][lo:hi]
-        assert (k[1:] > k[:-1]).all()
-    for b in (0, 7, 21, 33, 50, 63):
-        s0, s1 = int(offs[b]), int(offs[b + 1])
         r = oracle.downsample(x[s0:s1], y[s0:s1], z[s0:s1], rgb[s0:s1], float(leaves[b]))
-        lo, hi = int(oo[b]), int(oo[b + 1])
         fr = {k: g[k][lo:hi] for k in ("x", "y", "z", "rgb", "count", "key", "ref_index", "lx", "ly", "lz")}
         fr["point_cell"] = g["point_cell"][s0:s1]
         fr["m"] = hi - lo
         assert_matches_oracle(fr, r, float(leaves[b]), point_cell_offset=lo, ref_offset=s0)
+    print("case full batch: plain calls", flush=True)
+    for b in range(len(leaves)):
+        s0, s1 = int(offs[b]), int(offs[b + 1])
+        lo, hi = int(oo[b]), int(oo[b + 1])
+        p = gpu_downsample(x[s0:s1], y[s0:s1], z[s0:s1], rgb[s0:s1], float(leaves[b]), tuning=t)
+        assert p["m"] == hi - lo, b
+        for k in ("x", "y", "z", "rgb", "count", "key", "lx", "ly", "lz"):
+            assert np.array_equal(p[k].view(np.uint8), g[k][lo:hi].view(np.uint8)), (b, k)
+        assert np.array_equal(p["ref_index"].astype(np.int64) + s0, g["ref_index"][lo:hi])
+        pc = p["point_cell"].astype(np.int64)
+        assert np.array_equal(np.where(pc >= 0, pc + lo, -1), g["point_cell"][s0:s1]), b
+
+
+@pytest.mark.parametrize("mode", [vg.EXEC_PHASED, vg.EXEC_PERSISTENT])
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_device_timeout_marks_every_frame(mode, use_graph):
+    """A call whose device-side time-out flag is raised (from the host, so no
+    wait really runs out) reports VG_ERR_DEVICE in every frame; the plan's next
+    call is correct again."""
+    print(f"case simulated time-out, exec mode {mode}, graph {use_graph}", flush=True)
+    x, y, z, rgb, offs, leaves = small_batch(seed=7)
+    t = vg.default_tuning(exec_mode=mode)
+    plan = vg.BatchPlan(16, 400_000, vg.KEY_LINEAR, t, use_graph=use_graph)
+    good = run_batched(x, y, z, rgb, offs, leaves, plan=plan)
+    check_against_oracle(good, x, y, z, rgb, offs, leaves)
+    plan.set_fail_waits(True)
+    bad = run_batched(x, y, z, rgb, offs, leaves, plan=plan)
+    assert (bad["frame_status"] == vg.VG_ERR_DEVICE).all(), bad["frame_status"]
+    plan.set_fail_waits(False)
+    again = run_batched(x, y, z, rgb, offs, leaves, plan=plan)
+    check_against_oracle(again, x, y, z, rgb, offs, leaves)
+    plan.close()
 
 
 def many_frames(B, seed):

@@ -158,7 +158,8 @@ def test_deterministic():
 def supported_tunings():
     out = []
     for block, si, rb, ri in [(256, 16, 8, 8), (256, 8, 8, 8), (256, 12, 8, 8), (256, 16, 8, 4),
-                              (256, 16, 7, 8), (512, 8, 8, 4), (512, 8, 8, 8), (256, 16, 6, 8)]:
+                              (256, 16, 7, 8), (512, 8, 8, 4), (512, 8, 8, 8), (256, 16, 6, 8),
+                              (256, 8, 8, 4)]:
         for mode in (vg.EXEC_PERSISTENT, vg.EXEC_PHASED):
             out.append(dict(sort_block=block, sort_items=si, radix_bits=rb, reduce_block=block,
                             reduce_items=ri, exec_mode=mode))
