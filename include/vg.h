@@ -236,6 +236,27 @@ vg_status vg_batch_plan_set_fail_waits(vg_batch_plan *plan, int enable);
 /* Releases the plan (waits for its work to finish first). */
 vg_status vg_batch_plan_destroy(vg_batch_plan *plan);
 
+/* ---- a call that allocates nothing ----
+ * For callers that cannot allocate: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  The operation of
+ * vg_downsample_ex with the default tuning, but every scratch buffer (the
+ * sorted key/value table, look-back state, staged call header) lives in one
+ * fixed device array of VG_NOALLOC_SCRATCH_BYTES that the library holds on
+ * each GPU it runs on until the process ends; the call header goes to the
+ * device as kernel arguments, so no host buffer is used either.
+ * p, out: as vg_downsample_ex (device, capacity n); 0 <= n <=
+ * VG_NOALLOC_MAX_POINTS, else VG_ERR_WORKSPACE before anything is enqueued.
+ * d_m: device int64 [1], receives the number of cells (0 unless d_status is
+ * VG_OK); d_status: device int32 [1], receives VG_OK, VG_ERR_GRID_OVERFLOW or
+ * VG_ERR_DEVICE.  Fully asynchronous on `stream`: nothing is read back.
+ * Every call on one GPU shares that GPU's array, and each call clears the
+ * state it needs at its start: calls must be ordered (one stream, or
+ * synchronised); calls that overlap on one GPU race and give wrong results. */
+#define VG_NOALLOC_MAX_POINTS 1048576
+#define VG_NOALLOC_SCRATCH_BYTES (48u << 20)
+vg_status vg_downsample_noalloc(const vg_points *p, int64_t n, float leaf, vg_key_mode key_mode,
+                                vg_cells *out, int64_t *d_m, int32_t *d_status, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -354,10 +354,19 @@ vg_kernel_kind kind_of_phase(const Variant& v, int lo, int hi) {
 
 // Enqueues: staged copy, state reset, pipeline.  All launches have fixed
 // shapes (no per-call kernel arguments), so the sequence can be captured.
+vg_status enqueue_kernels(const Variant& v, const Ws& ws, int exec_mode, int cus, int bpc,
+                          hipStream_t s, LaunchTimer* tm = nullptr);
+
 vg_status enqueue(const Variant& v, const Layout& L, const Ws& ws, const char* staging,
                   int exec_mode, int cus, int bpc, hipStream_t s, LaunchTimer* tm = nullptr) {
   if (hipMemcpyAsync(ws.hdr, staging, L.staged, hipMemcpyHostToDevice, s) != hipSuccess)
     return VG_ERR_DEVICE;
+  return enqueue_kernels(v, ws, exec_mode, cus, bpc, s, tm);
+}
+
+// State reset, pipeline, status (the staged region must already be on its way).
+vg_status enqueue_kernels(const Variant& v, const Ws& ws, int exec_mode, int cus, int bpc,
+                          hipStream_t s, LaunchTimer* tm) {
   if (tm) tm->n = 0;
   auto mark = [&](int k, int which) {
     if (tm && tm->n < LaunchTimer::kMax) {
@@ -544,6 +553,80 @@ vg_status vg_downsample_backward(const float* gx, const float* gy, const float* 
                      static_cast<hipStream_t>(stream), gx, gy, gz, count, m, point_cell, n, dx, dy,
                      dz);
   return hipGetLastError() == hipSuccess ? VG_OK : VG_ERR_DEVICE;
+}
+
+}  // extern "C"
+
+// ============================================ calls that cannot allocate ====
+// The workspace of vg_downsample_noalloc: one fixed array per device, held
+// until the process ends.  Host code uses the device address that
+// hipGetSymbolAddress returns for it (scratch_base), never the array's name.
+static __device__ __align__(256) unsigned char scratch[VG_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch[64];
+
+// Device address of this device's scratch array (looked up once per device,
+// with that device current).
+void* scratch_base(int dev) {
+  if (dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    g_scratch[dev] = p;
+  }
+  return g_scratch[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+vg_status vg_downsample_noalloc(const vg_points* p, int64_t n, float leaf, vg_key_mode key_mode,
+                                vg_cells* out, int64_t* d_m, int32_t* d_status, void* stream) {
+  if (!p || !out || !d_m || !d_status) return VG_ERR_ARG;
+  if (n < 0 || (key_mode != VG_KEY_LINEAR && key_mode != VG_KEY_MORTON)) return VG_ERR_ARG;
+  if (n > VG_NOALLOC_MAX_POINTS) return VG_ERR_WORKSPACE;
+  if (n > 0 && (!p->x || !p->y || !p->z)) return VG_ERR_ARG;
+  if (!cells_consistent(out)) return VG_ERR_ARG;
+  float inv;
+  if (!leaf_inverse(leaf, &inv)) return VG_ERR_LEAF;
+  const Variant* v = find_variant(nullptr);
+  const Layout L = make_layout(std::max<int64_t>(n, 1), 1, *v);
+  if (L.total > sizeof(scratch) || L.staged > 8192) return VG_ERR_WORKSPACE;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return VG_ERR_DEVICE;
+  const int cus = device_cus(dev);
+  void* base = scratch_base(dev);
+  if (cus <= 0 || !base) return VG_ERR_DEVICE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Ws ws = carve(L, base);
+  // the staged region is built on the host as for the other calls, then
+  // passed by value to a one-thread kernel (no host buffer, no copy)
+  alignas(16) char st[8192];
+  const int64_t offs[2] = {0, n};
+  int64_t* w_off = reinterpret_cast<int64_t*>(static_cast<char*>(base) + L.outoff);
+  int32_t* w_st = reinterpret_cast<int32_t*>(static_cast<char*>(base) + L.fstat);
+  CallHdr hdr;
+  if (!fill_staging(st, L, *v, p, offs, &leaf, &inv, 1, out, w_off, w_st, key_mode, 0, &hdr))
+    return VG_ERR_ARG;
+  StageArgs a;
+  std::memcpy(&a.hdr, st + L.hdr, sizeof a.hdr);
+  std::memcpy(&a.io, st + L.io, sizeof a.io);
+  std::memcpy(&a.fd, st + L.fd, sizeof a.fd);
+  for (int k = 0; k < 2; ++k) {
+    a.tp[0][k] = reinterpret_cast<const uint32_t*>(st + L.tpb)[k];
+    a.tp[1][k] = reinterpret_cast<const uint32_t*>(st + L.tps)[k];
+    a.tp[2][k] = reinterpret_cast<const uint32_t*>(st + L.tpr)[k];
+  }
+  hipLaunchKernelGGL(vg_stage_kernel, dim3(1), dim3(64), 0, s, ws, a);
+  vg_status rc = enqueue_kernels(*v, ws, kDefaultTuning.exec_mode, cus, 0, s);
+  hipLaunchKernelGGL(vg_result_kernel, dim3(1), dim3(64), 0, s, ws, d_m, d_status);
+  if (rc == VG_OK && hipGetLastError() != hipSuccess) rc = VG_ERR_DEVICE;
+  return rc;
 }
 
 }  // extern "C"

@@ -2128,6 +2128,39 @@ __global__ void vg_status_kernel(Ws ws) {
   for (int b = threadIdx.x; b < hdr.B; b += blockDim.x) st[b] = kFrameDeviceError;
 }
 
+// A one-frame call's staged region passed by value (calls that copy nothing
+// from host memory): header, I/O pointers, frame description, tile prefixes.
+struct StageArgs {
+  CallHdr hdr;
+  Io io;
+  FrameDesc fd;
+  uint32_t tp[3][2];  // big / sort / reduce tile prefixes over the one frame
+};
+
+__global__ void vg_stage_kernel(Ws ws, StageArgs a) {
+  if (threadIdx.x != 0) return;
+  *ws.hdr = a.hdr;
+  *ws.io = a.io;
+  ws.fd[0] = a.fd;
+  ws.tpb[0] = a.tp[0][0];
+  ws.tpb[1] = a.tp[0][1];
+  ws.tps[0] = a.tp[1][0];
+  ws.tps[1] = a.tp[1][1];
+  ws.tpr[0] = a.tp[2][0];
+  ws.tpr[1] = a.tp[2][1];
+}
+
+// Result of a one-frame call on the device: its number of cells (0 unless the
+// frame is VG_OK) and its status.
+__global__ void vg_result_kernel(Ws ws, int64_t* m, int32_t* status) {
+  if (threadIdx.x != 0) return;
+  const Io io = *ws.io;
+  const uint32_t err = __hip_atomic_load(&ws.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int32_t st = err ? (int32_t)kFrameDeviceError : io.frame_status[0];
+  *status = st;
+  *m = st == kFrameOk ? io.out_offsets[1] - io.out_offsets[0] : 0;
+}
+
 // dL/dp_i = G[c] / count[c], c = point_cell[i]; zero where c < 0.
 __global__ void vg_backward_kernel(const float* gx, const float* gy, const float* gz,
                                    const uint32_t* count, int64_t m, const int32_t* pc, int64_t n,

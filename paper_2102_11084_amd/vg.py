@@ -59,7 +59,12 @@ _lib_handle = None
 EXPORTS = ["vg_status_string", "vg_default_tuning", "vg_tuning_supported", "vg_workspace_bytes",
            "vg_downsample", "vg_downsample_ex", "vg_downsample_backward", "vg_batch_plan_create",
            "vg_batch_plan_set_graph", "vg_downsample_batched", "vg_batch_plan_set_timing",
-           "vg_batch_plan_kernel_times", "vg_batch_plan_set_fail_waits", "vg_batch_plan_destroy"]
+           "vg_batch_plan_kernel_times", "vg_batch_plan_set_fail_waits", "vg_batch_plan_destroy",
+           "vg_downsample_noalloc"]
+
+# Largest cloud of vg_downsample_noalloc and the size of its fixed device array.
+NOALLOC_MAX_POINTS = 1048576
+NOALLOC_SCRATCH_BYTES = 48 << 20
 
 # vg_kernel_kind
 KERNEL_KINDS = ("init", "bbox", "hist", "sort", "reduce", "fixup", "pipeline")
@@ -92,6 +97,9 @@ def lib():
         L.vg_batch_plan_kernel_times.argtypes = [P, P, P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         L.vg_batch_plan_set_fail_waits.argtypes = [P, ctypes.c_int]
         L.vg_batch_plan_destroy.argtypes = [P]
+        L.vg_downsample_noalloc.argtypes = [ctypes.POINTER(vg_points), ctypes.c_int64,
+                                            ctypes.c_float, ctypes.c_int, ctypes.POINTER(vg_cells),
+                                            P, P, P]
         for name in EXPORTS:
             if name != "vg_status_string" and name != "vg_workspace_bytes":
                 getattr(L, name).restype = ctypes.c_int
@@ -193,6 +201,27 @@ def voxel_downsample(x, y, z, rgb=None, leaf=0.05, key_mode=KEY_LINEAR, tuning=N
     res = {k: (v if k == "point_cell" else v[:mm]) for k, v in o.items()}
     res["m"] = mm
     return res
+
+
+def voxel_downsample_noalloc(x, y, z, rgb=None, leaf=0.05, key_mode=KEY_LINEAR,
+                             outputs=ALL_OUTPUTS, out=None):
+    """vg_downsample_noalloc: the library allocates nothing (its workspace is a
+    fixed device array); fully asynchronous.  `out` = (tensors, vg_cells) from
+    an earlier call to reuse outputs; else they are allocated here (by torch,
+    for the caller).  Returns (untrimmed output tensors, m, status), m and
+    status as one-element device tensors."""
+    n = _check_points(x, y, z, rgb)
+    dev = x.device
+    o, cells = out if out is not None else _alloc_cells(max(n, 1), n, dev, outputs, rgb is not None)
+    dm = torch.empty(1, dtype=torch.int64, device=dev)
+    ds = torch.empty(1, dtype=torch.int32, device=dev)
+    pts = vg_points(_ptr(x), _ptr(y), _ptr(z), _ptr(rgb))
+    st = lib().vg_downsample_noalloc(ctypes.byref(pts), n, ctypes.c_float(leaf), int(key_mode),
+                                     ctypes.byref(cells), _ptr(dm), _ptr(ds),
+                                     ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream))
+    if st != VG_OK:
+        raise VGError(st, "vg_downsample_noalloc")
+    return o, dm, ds
 
 
 def downsample_backward(gx, gy, gz, count, point_cell):
