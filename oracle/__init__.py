@@ -62,6 +62,11 @@ def _bind(lib):
     lib.vgo_backward.restype = c_int
     lib.vgo_centroids_fixed.argtypes = [P, P, P, i64, P, i64, P, P, P]
     lib.vgo_centroids_fixed.restype = c_int
+    lib.vgo_philox4x64.argtypes = [P, P, P]
+    lib.vgo_philox4x64.restype = None
+    lib.vgo_nbd.argtypes = [P, P, P, i64, f32, f32, ctypes.c_uint32, ctypes.c_uint64, i64, P, P, P,
+                            i64, P]
+    lib.vgo_nbd.restype = c_int
     return lib
 
 
@@ -181,3 +186,35 @@ def centroids_fixed(x, y, z, point_cell, m, lib=None):
     if st != OK:
         raise OracleError(st)
     return cx[:m], cy[:m], cz[:m]
+
+
+def philox4x64(counter, key, lib=None):
+    """Philox4x64-10 of one 4-word counter under a 2-word key (4 uint64 words)."""
+    lib = lib or load()
+    c = np.ascontiguousarray(counter, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    out = np.zeros(4, np.uint64)
+    lib.vgo_philox4x64(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def nbd_decimate(x, y, z, leaf, radius, umbral, seed, round_size=1000, lib=None):
+    """Neighbour-bucket decimation (Alg. 1 of the paper, with the readings in
+    vgo.cpp): returns keep (bool [n]), count0 (neighbours before any deletion,
+    uint32 [n]), marked (points marked per round), rounds."""
+    lib = lib or load()
+    x, y, z = _f32(x), _f32(y), _f32(z)
+    n = x.size
+    keep = np.zeros(max(n, 1), np.uint8)
+    count0 = np.zeros(max(n, 1), np.uint32)
+    cap = 1 << 16
+    marked = np.zeros(cap, np.int64)
+    rounds = np.zeros(1, np.int64)
+    st = lib.vgo_nbd(_ptr(x), _ptr(y), _ptr(z), n, np.float32(leaf), np.float32(radius),
+                     int(umbral), int(seed), int(round_size), _ptr(keep), _ptr(count0),
+                     _ptr(marked), cap, _ptr(rounds))
+    if st != OK:
+        raise OracleError(st)
+    r = int(rounds[0])
+    return dict(keep=keep[:n].astype(bool), count0=count0[:n], marked=marked[:min(r, cap)],
+                rounds=r)

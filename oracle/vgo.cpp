@@ -34,10 +34,13 @@
 // "parity pinned": every entry point is checked by the CPU test suite against
 // closed forms, brute force and invariants.
 
+#include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <utility>
 #include <vector>
 
 namespace {
@@ -293,6 +296,175 @@ int vgo_centroids_fixed(const double* x, const double* y, const double* z, int64
     cy[k] = cnt[k] ? s[3 * k + 1] / nn : 0.0;
     cz[k] = cnt[k] ? s[3 * k + 2] / nn : 0.0;
   }
+  return VGO_OK;
+}
+
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Neighbour-bucket decimation (arXiv 2102.11084, Sec. II-C, Alg. 1).
+//
+// What the paper's own GPU filter computes, as read here:
+//   * the same grid as above (cubic cells of edge `leaf` anchored at the
+//     valid points' minimum) is the paper's regular decomposition of space;
+//     only the 27 cells around a point's cell are searched for its neighbours
+//     (Sec. II-C), with the Euclidean distance of Eq. (1);
+//   * q is a neighbour of p iff q != p, both are valid, their cell coordinates
+//     differ by at most 1 on every axis, and d2(p, q) <= r2, where
+//     d2 = RN32(RN32(RN32(dx*dx) + RN32(dy*dy)) + RN32(dz*dz)), dx = RN32(xq - xp)
+//     (and so on), r2 = RN32(radius * radius), 0 < radius <= leaf;
+//   * a round (Alg. 1, the loop body): every point still present counts its
+//     neighbours that are still present; it is marked when the count exceeds
+//     the threshold `umbral`; if more than `round_size` points are marked
+//     (1000 in the paper), `round_size` of them chosen at random are deleted
+//     for good and another round follows; otherwise the loop ends and every
+//     marked point is deleted (Alg. 1, the final deletion);
+//   * the random choice: marked point i gets the priority word 0 of
+//     Philox4x64-10 (Salmon et al., SC'11) at counter (i, round, 0, 0) under
+//     key (seed, 0); the `round_size` marked points of smallest
+//     (priority, i) are the ones deleted.
+// The oracle recounts every present point's neighbours in every round, from
+// neighbour lists built once by the 27-bucket search.
+
+namespace {
+
+const uint64_t kPhiloxM0 = 0xD2E7470EE14C6C93ull;
+const uint64_t kPhiloxM1 = 0xCA5A826395121157ull;
+const uint64_t kPhiloxW0 = 0x9E3779B97F4A7C15ull;
+const uint64_t kPhiloxW1 = 0xBB67AE8584CAA73Bull;
+
+void mulhilo64(uint64_t a, uint64_t b, uint64_t* hi, uint64_t* lo) {
+  unsigned __int128 p = (unsigned __int128)a * (unsigned __int128)b;
+  *hi = (uint64_t)(p >> 64);
+  *lo = (uint64_t)p;
+}
+
+// Philox4x64 with 10 rounds: each round multiplies words 0 and 2 by the two
+// round constants and mixes the halves with words 1 and 3 and the key; the
+// key advances by the two Weyl constants between rounds.
+void philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+  uint64_t c[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+  uint64_t k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += kPhiloxW0;
+      k1 += kPhiloxW1;
+    }
+    uint64_t hi0, lo0, hi1, lo1;
+    mulhilo64(kPhiloxM0, c[0], &hi0, &lo0);
+    mulhilo64(kPhiloxM1, c[2], &hi1, &lo1);
+    uint64_t n0 = hi1 ^ c[1] ^ k0;
+    uint64_t n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+  for (int i = 0; i < 4; ++i) out[i] = c[i];
+}
+
+float dist2(float ax, float ay, float az, float bx, float by, float bz) {
+  float dx = bx - ax;
+  float dy = by - ay;
+  float dz = bz - az;
+  float sx = dx * dx;
+  float sy = dy * dy;
+  float sz = dz * dz;
+  float sxy = sx + sy;
+  return sxy + sz;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Philox4x64-10 of one counter (exposed so the tests can check it against an
+// independent implementation).
+void vgo_philox4x64(const uint64_t* ctr, const uint64_t* key, uint64_t* out) {
+  philox4x64_10(ctr, key, out);
+}
+
+// Neighbour-bucket decimation of one cloud.  keep[i] = 1 for the points that
+// survive (invalid points never do); count0[i] = neighbours of i before any
+// deletion (0 for invalid points); marked[r] = points marked in round r for
+// r < cap_rounds; *rounds = rounds run.  Every output pointer but rounds may
+// be NULL.
+int vgo_nbd(const float* x, const float* y, const float* z, int64_t n, float leaf, float radius,
+            uint32_t umbral, uint64_t seed, int64_t round_size, uint8_t* keep, uint32_t* count0,
+            int64_t* marked, int64_t cap_rounds, int64_t* rounds) {
+  if (!rounds) return VGO_ERR_ARG;
+  *rounds = 0;
+  if (n < 0 || (n > 0 && (!x || !y || !z)) || round_size < 1 || cap_rounds < 0)
+    return VGO_ERR_ARG;
+  Grid g;
+  int st = make_grid(x, y, z, n, leaf, &g);
+  if (st != VGO_OK) return st;
+  if (!std::isfinite(radius) || !(radius > 0.0f) || !(radius <= leaf)) return VGO_ERR_ARG;
+  const float r2 = radius * radius;
+
+  // buckets: cell coordinates -> the valid points in it, ascending index
+  std::map<std::array<uint32_t, 3>, std::vector<int64_t>> bucket;
+  std::vector<std::array<uint32_t, 3>> cell((size_t)std::max<int64_t>(n, 1));
+  std::vector<uint8_t> valid((size_t)std::max<int64_t>(n, 1), 0);
+  for (int64_t i = 0; i < n; ++i) {
+    if (!point_is_valid(x[i], y[i], z[i])) continue;
+    valid[i] = 1;
+    cell[i] = {cell_coord(x[i], g.mn[0], g.inv), cell_coord(y[i], g.mn[1], g.inv),
+               cell_coord(z[i], g.mn[2], g.inv)};
+    bucket[cell[i]].push_back(i);
+  }
+  // neighbour lists by the 27-bucket search
+  std::vector<std::vector<int64_t>> nbr((size_t)std::max<int64_t>(n, 1));
+  for (int64_t i = 0; i < n; ++i) {
+    if (!valid[i]) continue;
+    for (int dz = -1; dz <= 1; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int64_t c[3] = {(int64_t)cell[i][0] + dx, (int64_t)cell[i][1] + dy,
+                                (int64_t)cell[i][2] + dz};
+          if (c[0] < 0 || c[1] < 0 || c[2] < 0) continue;
+          auto it = bucket.find({(uint32_t)c[0], (uint32_t)c[1], (uint32_t)c[2]});
+          if (it == bucket.end()) continue;
+          for (int64_t q : it->second) {
+            if (q == i) continue;
+            if (dist2(x[i], y[i], z[i], x[q], y[q], z[q]) <= r2) nbr[i].push_back(q);
+          }
+        }
+  }
+  std::vector<uint8_t> present(valid);
+  if (count0)
+    for (int64_t i = 0; i < n; ++i) count0[i] = valid[i] ? (uint32_t)nbr[i].size() : 0u;
+  const uint64_t key[2] = {seed, 0};
+  for (int64_t round = 0;; ++round) {
+    // count the present neighbours of every present point; mark
+    std::vector<int64_t> m;
+    for (int64_t i = 0; i < n; ++i) {
+      if (!present[i]) continue;
+      uint64_t cnt = 0;
+      for (int64_t q : nbr[i]) cnt += present[q];
+      if (cnt > umbral) m.push_back(i);
+    }
+    if (marked && round < cap_rounds) marked[round] = (int64_t)m.size();
+    *rounds = round + 1;
+    if ((int64_t)m.size() > round_size) {
+      // delete the round_size marked points of smallest (priority, index)
+      std::vector<std::pair<uint64_t, int64_t>> pri;
+      for (int64_t i : m) {
+        const uint64_t ctr[4] = {(uint64_t)i, (uint64_t)round, 0, 0};
+        uint64_t out[4];
+        philox4x64_10(ctr, key, out);
+        pri.push_back({out[0], i});
+      }
+      std::sort(pri.begin(), pri.end());
+      for (int64_t k = 0; k < round_size; ++k) present[pri[k].second] = 0;
+    } else {
+      for (int64_t i : m) present[i] = 0;
+      break;
+    }
+  }
+  if (keep)
+    for (int64_t i = 0; i < n; ++i) keep[i] = present[i];
   return VGO_OK;
 }
 

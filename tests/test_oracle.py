@@ -1,9 +1,10 @@
 """The CPU oracle against its pins (no GPU)."""
 import pytest
 
+import nbd_pins
 import oracle_pins as pins
 
 
-@pytest.mark.parametrize("pin", pins.ALL_PINS, ids=lambda f: f.__name__)
+@pytest.mark.parametrize("pin", pins.ALL_PINS + nbd_pins.ALL_NBD_PINS, ids=lambda f: f.__name__)
 def test_oracle_pin(pin, oracle_lib):
     pin(oracle_lib)

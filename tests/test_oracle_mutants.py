@@ -8,6 +8,7 @@ import os
 
 import pytest
 
+import nbd_pins
 import oracle
 import oracle_pins as pins
 
@@ -36,6 +37,20 @@ MUTANTS = {
     "fixed_constant_offset": ("cx[k] = cnt[k] ? s[3 * k + 0] / nn : 0.0;",
                               "cx[k] = cnt[k] ? s[3 * k + 0] / nn + 1e-3 : 0.0;"),
     "fixed_drops_row_0": ("if (c < 0 || c >= m) continue;", "if (c <= 0 || c >= m) continue;"),
+    # neighbour-bucket decimation
+    "nbd_threshold_inclusive": ("if (cnt > umbral) m.push_back(i);", "if (cnt >= umbral) m.push_back(i);"),
+    "nbd_loop_test_inclusive": ("if ((int64_t)m.size() > round_size) {", "if ((int64_t)m.size() >= round_size) {"),
+    "nbd_radius_exclusive": ("if (dist2(x[i], y[i], z[i], x[q], y[q], z[q]) <= r2)",
+                             "if (dist2(x[i], y[i], z[i], x[q], y[q], z[q]) < r2)"),
+    "nbd_drops_lower_z_cells": ("for (int dz = -1; dz <= 1; ++dz)", "for (int dz = 0; dz <= 1; ++dz)"),
+    "nbd_deletes_largest": ("std::sort(pri.begin(), pri.end());", "std::sort(pri.rbegin(), pri.rend());"),
+    "nbd_keeps_last_marked": ("for (int64_t i : m) present[i] = 0;\n      break;", "break;"),
+    "nbd_philox_no_key_bump": ("k0 += kPhiloxW0;", ""),
+    "nbd_round_in_wrong_word": ("{(uint64_t)i, (uint64_t)round, 0, 0}", "{(uint64_t)i, 0, (uint64_t)round, 0}"),
+    "nbd_deletes_one_fewer": ("for (int64_t k = 0; k < round_size; ++k)", "for (int64_t k = 1; k < round_size; ++k)"),
+    "nbd_counts_itself": ("if (q == i) continue;\n            if (dist2", "if (dist2"),
+    "nbd_dist_axis_slip": ("float dz = bz - az;", "float dz = by - ay;"),
+    "nbd_counts_deleted": ("for (int64_t q : nbr[i]) cnt += present[q];", "for (int64_t q : nbr[i]) cnt += 1;"),
 }
 
 
@@ -48,7 +63,7 @@ def test_mutant_is_caught(name, tmp_path):
     mpath.write_text(src.replace(old, new))
     lib = oracle.load(oracle.build(str(mpath), str(tmp_path / "libmutant.so")))
     caught = []
-    for pin in pins.ALL_PINS:
+    for pin in pins.ALL_PINS + nbd_pins.ALL_NBD_PINS:
         try:
             pin(lib)
         except Exception as err:  # any failure of a pin counts as catching the mutant
