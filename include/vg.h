@@ -236,6 +236,61 @@ vg_status vg_batch_plan_set_fail_waits(vg_batch_plan *plan, int enable);
 /* Releases the plan (waits for its work to finish first). */
 vg_status vg_batch_plan_destroy(vg_batch_plan *plan);
 
+/* ---- neighbour-bucket decimation: the paper's own GPU filter ----
+ * Sec. II-C and Alg. 1: space is cut into a regular grid (here the grid of
+ * vg_downsample: cubic cells of edge `leaf` anchored at the valid points'
+ * minimum), and a point's neighbours are searched in the 27 cells around its
+ * own, with the Euclidean distance of Eq. (1).  In rounds, every point still
+ * present counts its present neighbours and is marked if the count exceeds
+ * `umbral`; while more than `round_size` points are marked (1000 in the
+ * paper), `round_size` of them chosen at random are deleted and another round
+ * runs; the marked points of the last round are deleted too.  The survivors
+ * are handed back.  Readings of what the paper leaves open:
+ *   - q is a neighbour of p iff q != p, both are valid (finite), their cell
+ *     coordinates differ by at most 1 on every axis, and
+ *     RN32(RN32(RN32(dx*dx) + RN32(dy*dy)) + RN32(dz*dz)) <= RN32(radius^2),
+ *     dx = RN32(xq - xp) and so on; 0 < radius <= leaf, so the 27 cells hold
+ *     every point within the radius;
+ *   - the random choice: in round r, marked point i has the priority word 0
+ *     of Philox4x64-10 (Salmon et al., SC'11) at counter (i, r, 0, 0) under
+ *     key (seed, 0); the round_size marked points of smallest (priority, i)
+ *     are deleted. */
+typedef struct vg_nbd_params {
+  float leaf;           /* cell edge of the grid */
+  float radius;         /* neighbour radius, 0 < radius <= leaf */
+  uint32_t umbral;      /* a point with more neighbours than this is marked */
+  int32_t round_size;   /* points deleted per round while more are marked, >= 1 */
+  uint64_t seed;        /* key of the random choice */
+} vg_nbd_params;
+
+/* Outputs of a decimation; every pointer may be NULL.  Device arrays of
+ * capacity n unless noted. */
+typedef struct vg_nbd_out {
+  uint32_t *keep_index;  /* input indices of the survivors, ascending */
+  float *x, *y, *z;      /* the survivors' coordinates (complete triple or none) */
+  uint8_t *rgb;          /* their colours, n x 3 (written only if the input has rgb) */
+  uint32_t *count0;      /* every point's neighbours before any deletion (0 if invalid) */
+  int64_t *marked;       /* host [marked_cap]: points marked in round 0, 1, ... */
+  int64_t marked_cap;
+} vg_nbd_out;
+
+/* Device workspace of vg_nbd_decimate for n points (0 on bad arguments). */
+size_t vg_nbd_workspace_bytes(int64_t n, int32_t round_size);
+
+/* Neighbour-bucket decimation of one cloud (Sec. II-C, Alg. 1; readings
+ * above).  p: device points; 0 <= n < 2^30; o: stream, workspace (NULL: the
+ * call allocates its own) and tuning of the grid pipeline it runs first
+ * (o->key_mode is not used; o may be NULL).  *n_keep: survivors; *rounds:
+ * rounds run (the last one deletes every point it marks).  Synchronous: the
+ * rounds are enqueued in batches, and the host reads a device flag between
+ * batches to see whether the last round has run (the paper's loop test is a
+ * host decision too).  Errors: VG_ERR_ARG (also radius outside (0, leaf],
+ * round_size < 1), VG_ERR_LEAF, VG_ERR_WORKSPACE before any launch;
+ * VG_ERR_GRID_OVERFLOW, VG_ERR_DEVICE after. */
+vg_status vg_nbd_decimate(const vg_points *p, int64_t n, const vg_nbd_params *prm,
+                          vg_nbd_out *out, int64_t *n_keep, int64_t *rounds,
+                          const vg_options *o);
+
 /* ---- a call that allocates nothing ----
  * For callers that cannot allocate: code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc.  The operation of

@@ -11,6 +11,7 @@
 
 #include "../../include/vg.h"
 #include "vg_pipeline.hpp"
+#include "vg_nbd.hpp"
 
 namespace {
 
@@ -553,6 +554,258 @@ vg_status vg_downsample_backward(const float* gx, const float* gy, const float* 
                      static_cast<hipStream_t>(stream), gx, gy, gz, count, m, point_cell, n, dx, dy,
                      dz);
   return hipGetLastError() == hipSuccess ? VG_OK : VG_ERR_DEVICE;
+}
+
+}  // extern "C"
+
+// ==================================== neighbour-bucket decimation ====
+namespace {
+
+struct NbdLayout {
+  size_t ckey, ccount, pcell, ctl, seg, cursor, bsum, sx, sy, sz, sidx, scell, rng, cnt, alive,
+      hist, cand, del, mlog, keep, kpos, total;
+  uint32_t log_cap;
+  int scan_blocks;
+};
+
+// After the pipeline's own layout (which starts at 0).
+NbdLayout make_nbd_layout(size_t o, int64_t n, int64_t round_size) {
+  NbdLayout L;
+  const size_t N = (size_t)std::max<int64_t>(n, 1);
+  const size_t K = (size_t)std::max<int64_t>(1, std::min<int64_t>(round_size, (int64_t)N));
+  L.scan_blocks = (int)((N + kNbdScanTile - 1) / kNbdScanTile);
+  L.log_cap = (uint32_t)std::min<int64_t>((int64_t)N / (int64_t)K + 2, (int64_t)1 << 24);
+  o = align_up(o);
+  L.ckey = o;   o = align_up(o + 8 * N);
+  L.ccount = o; o = align_up(o + 4 * N);
+  L.pcell = o;  o = align_up(o + 4 * N);
+  L.ctl = o;    o = align_up(o + sizeof(NbdCtl));
+  L.seg = o;    o = align_up(o + 4 * (N + 1));
+  L.cursor = o; o = align_up(o + 4 * N);
+  L.bsum = o;   o = align_up(o + 4 * ((size_t)L.scan_blocks + 1));
+  L.sx = o;     o = align_up(o + 4 * N);
+  L.sy = o;     o = align_up(o + 4 * N);
+  L.sz = o;     o = align_up(o + 4 * N);
+  L.sidx = o;   o = align_up(o + 4 * N);
+  L.scell = o;  o = align_up(o + 4 * N);
+  L.rng = o;    o = align_up(o + 8 * 9 * N);
+  L.cnt = o;    o = align_up(o + 4 * N);
+  L.alive = o;  o = align_up(o + N);
+  L.hist = o;   o = align_up(o + 4 * (size_t)kNbdHistBins);
+  L.cand = o;   o = align_up(o + sizeof(NbdCand) * N);
+  L.del = o;    o = align_up(o + 4 * K);
+  L.mlog = o;   o = align_up(o + 8 * (size_t)L.log_cap);
+  L.keep = o;   o = align_up(o + 4 * N);
+  L.kpos = o;   o = align_up(o + 4 * (N + 1));
+  L.total = o;
+  return L;
+}
+
+struct NbdReadback {
+  uint32_t round, done;  // the same order as in NbdCtl: copied together
+  uint32_t nkeep, pad;
+  int32_t status;
+};
+
+int grid_for(int64_t items, int per_block, int cap) {
+  const int64_t b = (items + per_block - 1) / per_block;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, cap));
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t vg_nbd_workspace_bytes(int64_t n, int32_t round_size) {
+  if (n < 0 || n > kMaxFramePoints || round_size < 1) return 0;
+  const Variant* v = find_variant(nullptr);
+  const Layout L = make_layout(std::max<int64_t>(n, 1), 1, *v);
+  return make_nbd_layout(L.total, n, round_size).total;
+}
+
+vg_status vg_nbd_decimate(const vg_points* p, int64_t n, const vg_nbd_params* prm,
+                          vg_nbd_out* out, int64_t* n_keep, int64_t* rounds,
+                          const vg_options* o) {
+  if (n_keep) *n_keep = 0;
+  if (rounds) *rounds = 0;
+  if (!p || !prm || !out || !n_keep || !rounds) return VG_ERR_ARG;
+  if (n < 0 || n > kMaxFramePoints) return VG_ERR_ARG;
+  if (n > 0 && (!p->x || !p->y || !p->z)) return VG_ERR_ARG;
+  if (out->marked_cap < 0 || (out->marked_cap > 0 && !out->marked)) return VG_ERR_ARG;
+  const int nxyz = (out->x != nullptr) + (out->y != nullptr) + (out->z != nullptr);
+  if (nxyz != 0 && nxyz != 3) return VG_ERR_ARG;
+  if (prm->round_size < 1) return VG_ERR_ARG;
+  float inv;
+  if (!leaf_inverse(prm->leaf, &inv)) return VG_ERR_LEAF;
+  if (!std::isfinite(prm->radius) || !(prm->radius > 0.0f) || !(prm->radius <= prm->leaf))
+    return VG_ERR_ARG;
+  const vg_tuning* tuning = o ? o->tuning : nullptr;
+  const Variant* v = find_variant(tuning);
+  if (!v) return VG_ERR_ARG;
+  if (n == 0) {
+    *rounds = 1;  // one round that marks nothing
+    if (out->marked_cap > 0) out->marked[0] = 0;
+    return VG_OK;
+  }
+  const Layout L = make_layout(n, 1, *v);
+  const NbdLayout NL = make_nbd_layout(L.total, n, prm->round_size);
+  if (o && o->workspace && o->workspace_bytes < NL.total) return VG_ERR_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(o ? o->stream : nullptr);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return VG_ERR_DEVICE;
+  const int cus = device_cus(dev);
+  if (cus <= 0) return VG_ERR_DEVICE;
+  const int bpc = tuning ? tuning->blocks_per_cu : 0;
+  char* st = t_staging.get(L.staged + sizeof(NbdReadback));
+  if (!st) return VG_ERR_DEVICE;
+  void* base = o ? o->workspace : nullptr;
+  bool owned = false;
+  if (!base) {
+    if (hipMalloc(&base, NL.total) != hipSuccess) return VG_ERR_DEVICE;
+    owned = true;
+  }
+  char* b = static_cast<char*>(base);
+  Ws ws = carve(L, base);
+  NbdWs w;
+  w.ctl = reinterpret_cast<NbdCtl*>(b + NL.ctl);
+  w.x = p->x;
+  w.y = p->y;
+  w.z = p->z;
+  w.rgb = p->rgb;
+  w.n = n;
+  w.ckey = reinterpret_cast<uint64_t*>(b + NL.ckey);
+  w.ccount = reinterpret_cast<uint32_t*>(b + NL.ccount);
+  w.pcell = reinterpret_cast<int32_t*>(b + NL.pcell);
+  w.seg = reinterpret_cast<uint32_t*>(b + NL.seg);
+  w.cursor = reinterpret_cast<uint32_t*>(b + NL.cursor);
+  w.bsum = reinterpret_cast<uint32_t*>(b + NL.bsum);
+  w.sx = reinterpret_cast<float*>(b + NL.sx);
+  w.sy = reinterpret_cast<float*>(b + NL.sy);
+  w.sz = reinterpret_cast<float*>(b + NL.sz);
+  w.sidx = reinterpret_cast<uint32_t*>(b + NL.sidx);
+  w.scell = reinterpret_cast<uint32_t*>(b + NL.scell);
+  w.rng = reinterpret_cast<uint2*>(b + NL.rng);
+  w.cnt = reinterpret_cast<uint32_t*>(b + NL.cnt);
+  w.alive = reinterpret_cast<uint8_t*>(b + NL.alive);
+  w.hist = reinterpret_cast<uint32_t*>(b + NL.hist);
+  w.cand = reinterpret_cast<NbdCand*>(b + NL.cand);
+  w.del = reinterpret_cast<uint32_t*>(b + NL.del);
+  w.marked_log = reinterpret_cast<int64_t*>(b + NL.mlog);
+  w.keep = reinterpret_cast<uint32_t*>(b + NL.keep);
+  w.kpos = reinterpret_cast<uint32_t*>(b + NL.kpos);
+  w.count0 = out->count0;
+  w.keep_index = out->keep_index;
+  w.ox = out->x;
+  w.oy = out->y;
+  w.oz = out->z;
+  w.orgb = p->rgb ? out->rgb : nullptr;
+
+  // 1. the voxel pipeline: cell keys (linear), counts, every point's cell
+  vg_points pin = *p;
+  pin.rgb = nullptr;
+  vg_cells cells;
+  std::memset(&cells, 0, sizeof cells);
+  cells.key = w.ckey;
+  cells.count = w.ccount;
+  cells.point_cell = w.pcell;
+  const int64_t offs[2] = {0, n};
+  const float leaf = prm->leaf;
+  int64_t* d_off = reinterpret_cast<int64_t*>(b + L.outoff);
+  int32_t* d_st = reinterpret_cast<int32_t*>(b + L.fstat);
+  CallHdr hdr;
+  vg_status rc = VG_OK;
+  bool enqueued = false;
+  if (!fill_staging(st, L, *v, &pin, offs, &leaf, &inv, 1, &cells, d_off, d_st, VG_KEY_LINEAR, 0,
+                    &hdr)) {
+    rc = VG_ERR_ARG;
+  } else {
+    enqueued = true;
+    rc = enqueue(*v, L, ws, st, tuning ? tuning->exec_mode : kDefaultTuning.exec_mode, cus, bpc, s);
+  }
+  NbdReadback* rb = reinterpret_cast<NbdReadback*>(st + L.staged);
+  if (rc == VG_OK) {
+    // 2. buckets, neighbour ranges, counts
+    volatile float rr = prm->radius;
+    const float r2 = rr * rr;  // binary32, round to nearest even
+    const int nb = NL.scan_blocks;
+    hipLaunchKernelGGL(nbd_setup_kernel, dim3(grid_for(n, kNbdBlock, 1024)), dim3(kNbdBlock), 0, s,
+                       ws, w, prm->umbral, (uint32_t)prm->round_size, prm->seed, r2, NL.log_cap);
+    hipLaunchKernelGGL(nbd_scan_tiles, dim3(nb), dim3(kNbdBlock), 0, s, w.ccount, &w.ctl->m, w.bsum);
+    hipLaunchKernelGGL(nbd_scan_top, dim3(1), dim3(1024), 0, s, &w.ctl->m, w.bsum,
+                       &w.ctl->scan_total);
+    hipLaunchKernelGGL(nbd_scan_apply, dim3(nb), dim3(kNbdBlock), 0, s, w.ccount, &w.ctl->m,
+                       w.bsum, w.seg, w.cursor, &w.ctl->scan_total);
+    const int gp = grid_for(n, kNbdBlock, 8192);
+    hipLaunchKernelGGL(nbd_scatter_kernel, dim3(gp), dim3(kNbdBlock), 0, s, w);
+    hipLaunchKernelGGL(nbd_ranges_kernel, dim3(gp), dim3(kNbdBlock), 0, s, w);
+    hipLaunchKernelGGL(nbd_count_kernel, dim3(gp), dim3(kNbdBlock), 0, s, w);
+    // 3. rounds, enqueued in batches ahead of the host's look at the done flag
+    const int gr = grid_for(n, kNbdBlock, 2048);
+    const int gd = grid_for(std::min<int64_t>(prm->round_size, n), kNbdBlock / 64, 2048);
+    const int64_t max_rounds = n / prm->round_size + 2;
+    int64_t issued = 0;
+    int batch = 4;
+    for (;;) {
+      for (int r = 0; r < batch; ++r) {
+        hipLaunchKernelGGL(nbd_mark_kernel, dim3(gr), dim3(kNbdBlock), 0, s, w);
+        hipLaunchKernelGGL(nbd_select_kernel, dim3(1), dim3(1024), 0, s, w);
+        hipLaunchKernelGGL(nbd_collect_kernel, dim3(gr), dim3(kNbdBlock), 0, s, w);
+        hipLaunchKernelGGL(nbd_pick_kernel, dim3(1), dim3(kNbdBlock), 0, s, w);
+        hipLaunchKernelGGL(nbd_decrement_kernel, dim3(gd), dim3(kNbdBlock), 0, s, w);
+      }
+      issued += batch;
+      if (hipMemcpyAsync(&rb->round, &w.ctl->round, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                         s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess) {
+        rc = VG_ERR_DEVICE;
+        break;
+      }
+      if (rb->done) break;
+      if (issued > max_rounds) {  // every round but the last deletes round_size points
+        rc = VG_ERR_DEVICE;
+        break;
+      }
+      batch = std::min(batch * 2, 64);
+    }
+  }
+  if (rc == VG_OK) {
+    // 4. survivors in input order
+    hipLaunchKernelGGL(nbd_keep_kernel, dim3(grid_for(n, kNbdBlock, 8192)), dim3(kNbdBlock), 0, s, w);
+    const int nb = NL.scan_blocks;
+    hipLaunchKernelGGL(nbd_scan_tiles, dim3(nb), dim3(kNbdBlock), 0, s, w.keep, &w.ctl->n_in, w.bsum);
+    hipLaunchKernelGGL(nbd_scan_top, dim3(1), dim3(1024), 0, s, &w.ctl->n_in, w.bsum,
+                       &w.ctl->scan_total);
+    hipLaunchKernelGGL(nbd_scan_apply, dim3(nb), dim3(kNbdBlock), 0, s, w.keep, &w.ctl->n_in,
+                       w.bsum, w.kpos, nullptr, &w.ctl->scan_total);
+    hipLaunchKernelGGL(nbd_emit_kernel, dim3(grid_for(n, kNbdBlock, 8192)), dim3(kNbdBlock), 0, s, w);
+    const bool ok =
+        hipGetLastError() == hipSuccess &&
+        hipMemcpyAsync(&rb->round, &w.ctl->round, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s) ==
+            hipSuccess &&
+        hipMemcpyAsync(&rb->nkeep, &w.ctl->scan_total, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                       s) == hipSuccess &&
+        hipMemcpyAsync(&rb->status, &w.ctl->status, sizeof(int32_t), hipMemcpyDeviceToHost, s) ==
+            hipSuccess &&
+        hipStreamSynchronize(s) == hipSuccess;
+    if (!ok) {
+      rc = VG_ERR_DEVICE;
+    } else if (rb->status == kFrameOverflow) {
+      rc = VG_ERR_GRID_OVERFLOW;
+    } else if (rb->status != kFrameOk) {
+      rc = VG_ERR_DEVICE;
+    } else {
+      const int64_t nr = rb->round;
+      const int64_t nl = std::min<int64_t>(std::min<int64_t>(nr, out->marked_cap), NL.log_cap);
+      if (nl > 0 && (hipMemcpy(out->marked, w.marked_log, (size_t)nl * sizeof(int64_t),
+                               hipMemcpyDeviceToHost) != hipSuccess))
+        rc = VG_ERR_DEVICE;
+      *n_keep = rb->nkeep;
+      *rounds = nr;
+    }
+  }
+  if (owned || (enqueued && rc != VG_OK)) (void)hipStreamSynchronize(s);
+  if (owned) (void)hipFree(base);
+  return rc;
 }
 
 }  // extern "C"

@@ -47,6 +47,16 @@ class vg_options(ctypes.Structure):
                 ("key_mode", ctypes.c_int), ("tuning", ctypes.POINTER(vg_tuning))]
 
 
+class vg_nbd_params(ctypes.Structure):
+    _fields_ = [("leaf", ctypes.c_float), ("radius", ctypes.c_float), ("umbral", ctypes.c_uint32),
+                ("round_size", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+class vg_nbd_out(ctypes.Structure):
+    _fields_ = [("keep_index", P), ("x", P), ("y", P), ("z", P), ("rgb", P), ("count0", P),
+                ("marked", P), ("marked_cap", ctypes.c_int64)]
+
+
 class VGError(RuntimeError):
     def __init__(self, status, where=""):
         self.status = status
@@ -60,7 +70,7 @@ EXPORTS = ["vg_status_string", "vg_default_tuning", "vg_tuning_supported", "vg_w
            "vg_downsample", "vg_downsample_ex", "vg_downsample_backward", "vg_batch_plan_create",
            "vg_batch_plan_set_graph", "vg_downsample_batched", "vg_batch_plan_set_timing",
            "vg_batch_plan_kernel_times", "vg_batch_plan_set_fail_waits", "vg_batch_plan_destroy",
-           "vg_downsample_noalloc"]
+           "vg_downsample_noalloc", "vg_nbd_workspace_bytes", "vg_nbd_decimate"]
 
 # Largest cloud of vg_downsample_noalloc and the size of its fixed device array.
 NOALLOC_MAX_POINTS = 1048576
@@ -100,8 +110,14 @@ def lib():
         L.vg_downsample_noalloc.argtypes = [ctypes.POINTER(vg_points), ctypes.c_int64,
                                             ctypes.c_float, ctypes.c_int, ctypes.POINTER(vg_cells),
                                             P, P, P]
+        L.vg_nbd_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int32]
+        L.vg_nbd_workspace_bytes.restype = ctypes.c_size_t
+        L.vg_nbd_decimate.argtypes = [ctypes.POINTER(vg_points), ctypes.c_int64,
+                                      ctypes.POINTER(vg_nbd_params), ctypes.POINTER(vg_nbd_out),
+                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(vg_options)]
         for name in EXPORTS:
-            if name != "vg_status_string" and name != "vg_workspace_bytes":
+            if name not in ("vg_status_string", "vg_workspace_bytes", "vg_nbd_workspace_bytes"):
                 getattr(L, name).restype = ctypes.c_int
         _lib_handle = L
     return _lib_handle
@@ -222,6 +238,49 @@ def voxel_downsample_noalloc(x, y, z, rgb=None, leaf=0.05, key_mode=KEY_LINEAR,
     if st != VG_OK:
         raise VGError(st, "vg_downsample_noalloc")
     return o, dm, ds
+
+
+def nbd_decimate(x, y, z, rgb=None, leaf=0.02, radius=None, umbral=16, seed=1, round_size=1000,
+                 with_points=True, with_count0=False, workspace=None, tuning=None, marked_cap=1 << 16):
+    """Neighbour-bucket decimation (libvg: vg_nbd_decimate; the paper's Alg. 1).
+
+    Returns dict: keep_index (int32 view of uint32 input indices of the
+    survivors, ascending), x/y/z/rgb of the survivors (if with_points),
+    count0 (every point's neighbours before any deletion, if with_count0),
+    marked (numpy int64, points marked per round), rounds, n_keep."""
+    n = _check_points(x, y, z, rgb)
+    dev = x.device
+    radius = leaf if radius is None else radius
+    o = {"keep_index": torch.empty(max(n, 1), dtype=torch.int32, device=dev)}
+    if with_points:
+        o["x"], o["y"], o["z"] = (torch.empty(max(n, 1), dtype=torch.float32, device=dev)
+                                  for _ in range(3))
+        if rgb is not None:
+            o["rgb"] = torch.empty((max(n, 1), 3), dtype=torch.uint8, device=dev)
+    if with_count0:
+        o["count0"] = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    marked = np.zeros(marked_cap, np.int64)
+    out = vg_nbd_out(_ptr(o["keep_index"]), _ptr(o.get("x")), _ptr(o.get("y")), _ptr(o.get("z")),
+                     _ptr(o.get("rgb")), _ptr(o.get("count0")), ctypes.c_void_p(marked.ctypes.data),
+                     marked_cap)
+    prm = vg_nbd_params(float(leaf), float(radius), int(umbral), int(round_size), int(seed))
+    wsb = int(lib().vg_nbd_workspace_bytes(max(n, 1), int(round_size)))
+    if workspace is None or workspace.numel() < wsb:
+        workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    opts = vg_options(ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream),
+                      ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), KEY_LINEAR,
+                      ctypes.pointer(tuning) if tuning is not None else None)
+    nk, nr = ctypes.c_int64(0), ctypes.c_int64(0)
+    pts = vg_points(_ptr(x), _ptr(y), _ptr(z), _ptr(rgb))
+    st = lib().vg_nbd_decimate(ctypes.byref(pts), n, ctypes.byref(prm), ctypes.byref(out),
+                               ctypes.byref(nk), ctypes.byref(nr), ctypes.byref(opts))
+    if st != VG_OK:
+        raise VGError(st, "vg_nbd_decimate")
+    k, r = int(nk.value), int(nr.value)
+    res = {key: (v if key == "count0" else v[:k]) for key, v in o.items()}
+    res["n_keep"], res["rounds"] = k, r
+    res["marked"] = marked[:min(r, marked_cap)].copy()
+    return res
 
 
 def downsample_backward(gx, gy, gz, count, point_cell):
