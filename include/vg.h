@@ -261,7 +261,14 @@ typedef struct vg_nbd_params {
   uint32_t umbral;      /* a point with more neighbours than this is marked */
   int32_t round_size;   /* points deleted per round while more are marked, >= 1 */
   uint64_t seed;        /* key of the random choice */
+  uint32_t flags;       /* VG_NBD_* bits */
+  uint32_t reserved;    /* 0 */
 } vg_nbd_params;
+
+/* Choose each round's deletions by the exact select over every marked point
+ * instead of ranking the candidates of a priority window first.  Slower; the
+ * deletions are the same (the window only ever narrows the search). */
+#define VG_NBD_EXACT_SELECT 1u
 
 /* Outputs of a decimation; every pointer may be NULL.  Device arrays of
  * capacity n unless noted. */

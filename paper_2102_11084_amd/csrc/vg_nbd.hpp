@@ -11,14 +11,17 @@
 //   count     per point, its neighbours: points of the 9 ranges within the
 //             radius (Eq. (1), in binary32 with one rounding per operation)
 // and then rounds (Alg. 1's loop), each five launches:
-//   mark      points present with more than `umbral` neighbours are marked;
-//             their Philox priorities' top 16 bits are counted
-//   select    (one workgroup) if at most round_size are marked this is the last
-//             round; else the priority bucket holding the round_size-th smallest
-//   collect   marked points below that bucket are deleted, those in it become
-//             candidates; in the last round every marked point is deleted
-//   pick      (one workgroup) radix select of the remaining candidates by
-//             (priority, index); deleted; the round counter advances
+//   mark      points present with more than `umbral` neighbours are flagged;
+//             each workgroup counts its flags
+//   select    (one workgroup) the round's marked count; if at most round_size
+//             this is the last round; else a priority window expected to hold
+//             the round_size smallest priorities (with a wide margin)
+//   collect   in the last round every marked point is deleted; otherwise the
+//             marked points in the window become candidates
+//   pick      (one workgroup) the round_size candidates of smallest (priority,
+//             index), each ranked against the others in LDS, are deleted (an
+//             exact radix select over every marked point when the window
+//             falls short); the round counter advances
 //   decrement the neighbours of every point deleted in the round lose one
 //             from their count (no recount: a count only ever changes by the
 //             deletions around it)
@@ -32,7 +35,7 @@ namespace vg {
 
 constexpr int kNbdBlock = 256;
 constexpr int kNbdScanTile = 4096;      // elements per workgroup of the scans
-constexpr int kNbdHistBins = 1 << 16;   // top 16 bits of a priority
+constexpr int kNbdMarkBlocks = 1024;    // workgroups of the mark launch
 
 struct NbdCtl {
   float mn[3];
@@ -58,6 +61,9 @@ struct NbdCtl {
   uint32_t nkeep;       // survivors
   uint32_t log_cap;     // entries of marked_log
   uint32_t scan_total;  // total of the last scan
+  uint32_t exact;       // select through the exact path only
+  uint32_t pad2;
+  uint64_t window;      // candidates: marked points with a priority below this
 };
 
 static_assert(offsetof(NbdCtl, done) == offsetof(NbdCtl, round) + 4, "round, done adjacent");
@@ -89,7 +95,8 @@ struct NbdWs {
   uint2* rng;           // [n * 9] point ranges of the 9 neighbour runs of a cell
   uint32_t* cnt;        // [n] present neighbours
   uint8_t* alive;       // [n]
-  uint32_t* hist;       // [kNbdHistBins]
+  uint8_t* mflag;       // [n] marked in the current round
+  uint32_t* partial;    // [mark workgroups] marked per workgroup
   NbdCand* cand;        // [n]
   uint32_t* del;        // [round_size]
   int64_t* marked_log;  // [log_cap]
@@ -146,10 +153,9 @@ __device__ __forceinline__ uint64_t nbd_priority(const NbdCtl& c, uint32_t idx, 
 // Grid of the cloud from the pipeline's workspace (the same frame parameters
 // its kernels used), the call's constants, and cleared tables.
 __global__ void nbd_setup_kernel(Ws pws, NbdWs w, uint32_t umbral, uint32_t round_size,
-                                 uint64_t seed, float r2, uint32_t log_cap) {
+                                 uint64_t seed, float r2, uint32_t log_cap, uint32_t exact) {
   const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t nth = (size_t)gridDim.x * blockDim.x;
-  for (size_t i = tid; i < (size_t)kNbdHistBins; i += nth) w.hist[i] = 0u;
   for (size_t i = tid; i < (size_t)w.n; i += nth) {
     w.keep[i] = 0u;
     if (w.count0) w.count0[i] = 0u;
@@ -176,6 +182,7 @@ __global__ void nbd_setup_kernel(Ws pws, NbdWs w, uint32_t umbral, uint32_t roun
   c.seed = seed;
   c.n_in = (uint32_t)w.n;
   c.log_cap = log_cap;
+  c.exact = exact;
   // nothing to decimate: the loop is already over (one empty round)
   if (c.status != kFrameOk) c.done = 1;
   *w.ctl = c;
@@ -323,168 +330,277 @@ __global__ __launch_bounds__(kNbdBlock) void nbd_count_kernel(NbdWs w) {
 }
 
 // ----------------------------------------------------------- rounds ----
+// Marked points are flagged, and every workgroup writes its count of them.
 __global__ __launch_bounds__(kNbdBlock) void nbd_mark_kernel(NbdWs w) {
   const NbdCtl c = *w.ctl;
   if (c.done) return;
-  if (blockIdx.x == 0 && threadIdx.x == 0) w.ctl->ndel = 0u;  // the last round's deletions are done
+  if (blockIdx.x == 0 && threadIdx.x == 0) {  // the last round's lists are used up
+    w.ctl->ndel = 0u;
+    w.ctl->ncand = 0u;
+  }
   const uint32_t nth = gridDim.x * blockDim.x;
-  const uint32_t lane = threadIdx.x & 63;
+  uint32_t total = 0;
   for (uint32_t j0 = blockIdx.x * blockDim.x; j0 < c.nv; j0 += nth) {
     const uint32_t j = j0 + threadIdx.x;
     bool mk = false;
-    if (j < c.nv && w.alive[j] && w.cnt[j] > c.umbral) {
-      mk = true;
-      const uint64_t pri = nbd_priority(c, w.sidx[j], c.round);
-      atomicAdd(&w.hist[(uint32_t)(pri >> 48)], 1u);
+    if (j < c.nv) {
+      mk = w.alive[j] && w.cnt[j] > c.umbral;
+      w.mflag[j] = mk ? 1 : 0;
     }
-    const uint64_t b = __ballot(mk);
-    if (lane == 0 && b) atomicAdd(&w.ctl->marked, (uint32_t)__popcll(b));
+    total += (uint32_t)__syncthreads_count(mk);
   }
+  if (threadIdx.x == 0) w.partial[blockIdx.x] = total;
 }
 
-__global__ __launch_bounds__(1024) void nbd_select_kernel(NbdWs w) {
+// One workgroup: the round's marked count; the last round if it is at most
+// round_size; else the priority window [0, T) expected to hold the round_size
+// smallest priorities with a margin of 8 standard deviations (priorities are
+// uniform: the count below T is binomial).  T only limits which points are
+// candidates, never which are deleted.
+__global__ __launch_bounds__(1024) void nbd_select_kernel(NbdWs w, uint32_t nparts) {
   __shared__ uint32_t ws[1024 / 64];
-  __shared__ uint32_t found[2];
   if (w.ctl->done) return;
-  const uint32_t M = w.ctl->marked;
   const uint32_t K = w.ctl->round_size;
   const uint32_t round = w.ctl->round;
-  __syncthreads();  // every thread has read the counters before thread 0 resets them
-  constexpr int PER = kNbdHistBins / 1024;
-  const uint32_t t = threadIdx.x;
-  if (M > K) {
-    uint32_t h[PER];
-    uint32_t s = 0;
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      h[k] = w.hist[t * PER + k];
-      s += h[k];
+  uint32_t s = 0;
+  for (uint32_t i = threadIdx.x; i < nparts; i += 1024) s += w.partial[i];
+  uint32_t M;
+  (void)block_excl_scan<1024>(s, ws, M);
+  if (threadIdx.x == 0) {
+    if (round < w.ctl->log_cap) w.marked_log[round] = (int64_t)M;
+    w.ctl->marked = M;
+    w.ctl->last = M <= K ? 1u : 0u;
+    uint64_t T = ~0ull;
+    if (M > K) {
+      const double want = (double)K + 8.0 * sqrt((double)K) + 32.0;
+      const double r = want / (double)M;
+      if (r < 1.0) T = (uint64_t)(r * 18446744073709551616.0);
+    }
+    w.ctl->window = T;
+  }
+}
+
+// In the last round every marked point is deleted; otherwise the marked
+// points with a priority below the window become candidates.  Appends are
+// gathered per workgroup (one atomic each).
+__global__ __launch_bounds__(kNbdBlock) void nbd_collect_kernel(NbdWs w) {
+  __shared__ uint32_t ws[kNbdBlock / 64];
+  __shared__ uint32_t base_s;
+  const NbdCtl c = *w.ctl;
+  if (c.done || (!c.last && c.exact)) return;
+  const uint32_t nth = gridDim.x * blockDim.x;
+  for (uint32_t j0 = blockIdx.x * blockDim.x; j0 < c.nv; j0 += nth) {
+    const uint32_t j = j0 + threadIdx.x;
+    bool sel = false;
+    uint64_t pri = 0;
+    if (j < c.nv && w.mflag[j]) {
+      if (c.last) {
+        sel = true;
+      } else {
+        pri = nbd_priority(c, w.sidx[j], c.round);
+        sel = pri < c.window;
+      }
     }
     uint32_t tot;
-    const uint32_t before = block_excl_scan<1024>(s, ws, tot);
-    if (before < K && K <= before + s) {
-      uint32_t run = before;
-      for (int k = 0; k < PER; ++k) {
-        if (run + h[k] >= K) {
-          found[0] = t * PER + k;
-          found[1] = K - run;
-          break;
-        }
-        run += h[k];
+    const uint32_t off = block_excl_scan<kNbdBlock>(sel ? 1u : 0u, ws, tot);
+    if (tot == 0) continue;
+    if (threadIdx.x == 0) base_s = atomicAdd(c.last ? &w.ctl->ndel : &w.ctl->ncand, tot);
+    __syncthreads();
+    if (sel) {
+      const uint32_t at = base_s + off;
+      if (c.last) {
+        w.del[at] = j;
+        w.alive[j] = 0;
+      } else {
+        NbdCand cd;
+        cd.pri = pri;
+        cd.idx = w.sidx[j];
+        cd.pos = j;
+        w.cand[at] = cd;
       }
     }
-    __syncthreads();
-  }
-  // cleared for the next round (every bin was read above)
-#pragma unroll
-  for (int k = 0; k < PER; ++k) w.hist[t * PER + k] = 0u;
-  if (t == 0) {
-    if (round < w.ctl->log_cap) w.marked_log[round] = (int64_t)M;
-    w.ctl->marked = 0u;
-    w.ctl->ncand = 0u;
-    if (M > K) {
-      w.ctl->last = 0u;
-      w.ctl->bstar = found[0];
-      w.ctl->need = found[1];
-    } else {
-      w.ctl->last = 1u;
-      w.ctl->bstar = 0u;
-      w.ctl->need = 0u;
-    }
+    __syncthreads();  // base_s is reused
   }
 }
 
-__global__ __launch_bounds__(kNbdBlock) void nbd_collect_kernel(NbdWs w) {
-  const NbdCtl c = *w.ctl;
-  if (c.done) return;
-  const uint32_t nth = gridDim.x * blockDim.x;
-  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < c.nv; j += nth) {
-    if (!w.alive[j] || w.cnt[j] <= c.umbral) continue;
-    if (c.last) {
-      w.del[atomicAdd(&w.ctl->ndel, 1u)] = j;
-      w.alive[j] = 0;
-      continue;
-    }
-    const uint64_t pri = nbd_priority(c, w.sidx[j], c.round);
-    const uint32_t top = (uint32_t)(pri >> 48);
-    if (top < c.bstar) {
-      w.del[atomicAdd(&w.ctl->ndel, 1u)] = j;
-      w.alive[j] = 0;
-    } else if (top == c.bstar) {
-      NbdCand cd;
-      cd.pri = pri;
-      cd.idx = w.sidx[j];
-      cd.pos = j;
-      w.cand[atomicAdd(&w.ctl->ncand, 1u)] = cd;
-    }
-  }
+__device__ __forceinline__ bool nbd_key_less(uint64_t pa, uint32_t ia, uint64_t pb, uint32_t ib) {
+  return pa < pb || (pa == pb && ia < ib);
 }
 
-// One workgroup: the `need` candidates of smallest (priority, index) are
-// deleted.  Radix select, most significant byte first, over the 48 low bits
-// of the priority (the top 16 are the bucket's) and then the 32 index bits;
-// the key found last is the need-th smallest, and every candidate at or below
-// it goes.  Keys are distinct (indices are), so exactly `need` go.
-__global__ __launch_bounds__(kNbdBlock) void nbd_pick_kernel(NbdWs w) {
+constexpr int kPickBlock = 1024;
+constexpr int kPickCap = 4096;   // candidates bucketed in LDS
+constexpr int kPickBins = 4096;  // buckets of the window
+constexpr int kPickEdge = 256;   // candidates of the boundary bucket ranked in LDS
+
+// One workgroup: the round_size marked points of smallest (priority, index)
+// are deleted.  Usually from the window's candidates: they are counted into
+// 4096 buckets by their priority's leading bits (priorities in the window are
+// uniform, so a bucket holds about one); a block scan finds the bucket that
+// holds the round_size-th smallest; candidates in lower buckets go, and those
+// in that bucket are ranked against each other.  When the window holds fewer
+// than round_size candidates (or more than fit in LDS), or the exact path is
+// asked for, a radix select over every marked point, most significant byte
+// first over the 64 priority bits and then the 32 index bits, decides
+// instead.  Keys are distinct (indices are), so exactly round_size go.
+__global__ __launch_bounds__(kPickBlock) void nbd_pick_kernel(NbdWs w) {
+  __shared__ uint64_t cp[kPickCap];
+  __shared__ uint32_t ci[kPickCap];
+  __shared__ uint32_t cpos[kPickCap];
+  __shared__ uint32_t hb[kPickBins];
+  __shared__ uint64_t ep[kPickEdge];
+  __shared__ uint32_t ei[kPickEdge], epos[kPickEdge];
+  __shared__ uint32_t ws[kPickBlock / 64];
   __shared__ uint32_t h[256];
   __shared__ uint64_t pfx_pri;
-  __shared__ uint32_t pfx_idx, need_s;
-  if (w.ctl->done) return;
+  __shared__ uint32_t pfx_idx, need_s, ndel_s, bnd_s, nedge_s;
+  const NbdCtl c = *w.ctl;
+  if (c.done) return;
   const uint32_t t = threadIdx.x;
-  if (!w.ctl->last) {
-    const uint32_t nc = w.ctl->ncand;
-    if (t == 0) {
-      pfx_pri = (uint64_t)w.ctl->bstar << 48;
-      pfx_idx = 0u;
-      need_s = w.ctl->need;
-    }
-    __syncthreads();
-    for (int level = 0; level < 10; ++level) {
-      h[t] = 0u;
-      __syncthreads();
-      // bits of the key fixed so far: 16 + 8 * level of the priority, then index
-      const int pbits = min(64, 16 + 8 * level);
-      const int ibits = max(0, 8 * level - 48);
-      const uint64_t pmask = pbits >= 64 ? ~0ull : ~((1ull << (64 - pbits)) - 1ull);
-      const uint32_t imask = ibits == 0 ? 0u : ~((1u << (32 - ibits)) - 1u);  // ibits <= 24
-      const uint64_t pp = pfx_pri;
-      const uint32_t pi = pfx_idx;
-      for (uint32_t k = t; k < nc; k += kNbdBlock) {
-        const NbdCand cd = w.cand[k];
-        if ((cd.pri & pmask) != pp || (cd.idx & imask) != pi) continue;
-        const uint32_t dig = level < 6 ? (uint32_t)(cd.pri >> (40 - 8 * level)) & 255u
-                                       : (cd.idx >> (24 - 8 * (level - 6))) & 255u;
-        atomicAdd(&h[dig], 1u);
+  const uint32_t K = c.round_size;
+  if (!c.last) {
+    const uint32_t nc = c.ncand;
+    if (!c.exact && nc >= K && nc <= (uint32_t)kPickCap) {
+      // bucket of a priority in [0, window): its leading bits below the
+      // window's top bit, 12 of them
+      const int wbits = c.window == ~0ull ? 64 : 64 - __clzll(c.window);
+      const int shift = max(0, wbits - 12);
+      for (uint32_t k = t; k < (uint32_t)kPickBins; k += kPickBlock) hb[k] = 0u;
+      if (t == 0) {
+        ndel_s = 0u;
+        nedge_s = 0u;
       }
       __syncthreads();
-      if (t == 0) {
-        uint32_t run = 0, need = need_s;
-        for (uint32_t dgt = 0; dgt < 256; ++dgt) {
-          if (run + h[dgt] >= need) {
-            need_s = need - run;
-            if (level < 6) pfx_pri = pp | ((uint64_t)dgt << (40 - 8 * level));
-            else pfx_idx = pi | (dgt << (24 - 8 * (level - 6)));
-            break;
+      for (uint32_t k = t; k < nc; k += kPickBlock) {
+        const NbdCand cd = w.cand[k];
+        cp[k] = cd.pri;
+        ci[k] = cd.idx;
+        cpos[k] = cd.pos;
+        atomicAdd(&hb[(uint32_t)(cd.pri >> shift) & (kPickBins - 1)], 1u);
+      }
+      __syncthreads();
+      constexpr int PB = kPickBins / kPickBlock;
+      uint32_t v[PB], sum = 0;
+#pragma unroll
+      for (int q = 0; q < PB; ++q) {
+        v[q] = hb[t * PB + q];
+        sum += v[q];
+      }
+      uint32_t tot;
+      uint32_t run = block_excl_scan<kPickBlock>(sum, ws, tot);
+      if (run < K && K <= run + sum) {
+#pragma unroll
+        for (int q = 0; q < PB; ++q) {
+          if (run < K && K <= run + v[q]) {
+            bnd_s = t * PB + q;
+            need_s = K - run;
           }
-          run += h[dgt];
+          run += v[q];
         }
       }
       __syncthreads();
-    }
-    const uint64_t tp = pfx_pri;
-    const uint32_t ti = pfx_idx;
-    for (uint32_t k = t; k < nc; k += kNbdBlock) {
-      const NbdCand cd = w.cand[k];
-      if (cd.pri < tp || (cd.pri == tp && cd.idx <= ti)) {
-        w.del[atomicAdd(&w.ctl->ndel, 1u)] = cd.pos;
-        w.alive[cd.pos] = 0;
+      const uint32_t bnd = bnd_s;
+      for (uint32_t k = t; k < nc; k += kPickBlock) {
+        const uint32_t bk = (uint32_t)(cp[k] >> shift) & (kPickBins - 1);
+        if (bk < bnd) {
+          w.del[atomicAdd(&ndel_s, 1u)] = cpos[k];
+          w.alive[cpos[k]] = 0;
+        } else if (bk == bnd) {
+          const uint32_t e = atomicAdd(&nedge_s, 1u);
+          if (e < (uint32_t)kPickEdge) {
+            ep[e] = cp[k];
+            ei[e] = ci[k];
+            epos[e] = cpos[k];
+          }
+        }
       }
+      __syncthreads();
+      const uint32_t ne = min(nedge_s, (uint32_t)kPickEdge);
+      if (nedge_s <= (uint32_t)kPickEdge) {
+        // rank within the boundary bucket; the need_s smallest go
+        if (t < ne) {
+          uint32_t rank = 0;
+          for (uint32_t k = 0; k < ne; ++k) rank += nbd_key_less(ep[k], ei[k], ep[t], ei[t]) ? 1u : 0u;
+          if (rank < need_s) {
+            w.del[atomicAdd(&ndel_s, 1u)] = epos[t];
+            w.alive[epos[t]] = 0;
+          }
+        }
+      } else {
+        // a crowded boundary bucket (not expected): rank its members against
+        // all candidates of the bucket, read from the candidate list
+        for (uint32_t k = t; k < nc; k += kPickBlock) {
+          if (((uint32_t)(cp[k] >> shift) & (kPickBins - 1)) != bnd) continue;
+          uint32_t rank = 0;
+          for (uint32_t q = 0; q < nc; ++q)
+            rank += (((uint32_t)(cp[q] >> shift) & (kPickBins - 1)) == bnd &&
+                     nbd_key_less(cp[q], ci[q], cp[k], ci[k])) ? 1u : 0u;
+          if (rank < need_s) {
+            w.del[atomicAdd(&ndel_s, 1u)] = cpos[k];
+            w.alive[cpos[k]] = 0;
+          }
+        }
+      }
+      __syncthreads();
+      if (t == 0) w.ctl->ndel = ndel_s;
+    } else {
+      // exact path over every marked point
+      if (t == 0) {
+        pfx_pri = 0ull;
+        pfx_idx = 0u;
+        need_s = K;
+        ndel_s = 0u;
+      }
+      __syncthreads();
+      for (int level = 0; level < 12; ++level) {
+        if (t < 256) h[t] = 0u;
+        __syncthreads();
+        const int pbits = min(64, 8 * level);
+        const int ibits = max(0, 8 * level - 64);
+        const uint64_t pmask = pbits == 0 ? 0ull : (pbits >= 64 ? ~0ull : ~((1ull << (64 - pbits)) - 1ull));
+        const uint32_t imask = ibits == 0 ? 0u : ~((1u << (32 - ibits)) - 1u);  // ibits <= 24
+        const uint64_t pp = pfx_pri;
+        const uint32_t pi = pfx_idx;
+        for (uint32_t j = t; j < c.nv; j += kPickBlock) {
+          if (!w.mflag[j]) continue;
+          const uint32_t idx = w.sidx[j];
+          const uint64_t pri = nbd_priority(c, idx, c.round);
+          if ((pri & pmask) != pp || (idx & imask) != pi) continue;
+          const uint32_t dig = level < 8 ? (uint32_t)(pri >> (56 - 8 * level)) & 255u
+                                         : (idx >> (24 - 8 * (level - 8))) & 255u;
+          atomicAdd(&h[dig], 1u);
+        }
+        __syncthreads();
+        const uint32_t hv = t < 256 ? h[t] : 0u;
+        uint32_t tot;
+        const uint32_t before = block_excl_scan<kPickBlock>(hv, ws, tot);
+        const uint32_t need = need_s;
+        __syncthreads();
+        if (t < 256 && before < need && need <= before + hv) {
+          need_s = need - before;
+          if (level < 8) pfx_pri = pp | ((uint64_t)t << (56 - 8 * level));
+          else pfx_idx = pi | (t << (24 - 8 * (level - 8)));
+        }
+        __syncthreads();
+      }
+      const uint64_t tp = pfx_pri;
+      const uint32_t ti = pfx_idx;
+      for (uint32_t j = t; j < c.nv; j += kPickBlock) {
+        if (!w.mflag[j]) continue;
+        const uint32_t idx = w.sidx[j];
+        const uint64_t pri = nbd_priority(c, idx, c.round);
+        if (!nbd_key_less(tp, ti, pri, idx)) {  // key <= the round_size-th smallest
+          w.del[atomicAdd(&ndel_s, 1u)] = j;
+          w.alive[j] = 0;
+        }
+      }
+      __syncthreads();
+      if (t == 0) w.ctl->ndel = ndel_s;
     }
   }
   __syncthreads();
   if (t == 0) {
-    w.ctl->round = w.ctl->round + 1u;
-    if (w.ctl->last) w.ctl->done = 1u;
+    w.ctl->round = c.round + 1u;
+    if (c.last) w.ctl->done = 1u;
   }
 }
 

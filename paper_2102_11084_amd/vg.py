@@ -49,7 +49,11 @@ class vg_options(ctypes.Structure):
 
 class vg_nbd_params(ctypes.Structure):
     _fields_ = [("leaf", ctypes.c_float), ("radius", ctypes.c_float), ("umbral", ctypes.c_uint32),
-                ("round_size", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("round_size", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+NBD_EXACT_SELECT = 1
 
 
 class vg_nbd_out(ctypes.Structure):
@@ -241,7 +245,8 @@ def voxel_downsample_noalloc(x, y, z, rgb=None, leaf=0.05, key_mode=KEY_LINEAR,
 
 
 def nbd_decimate(x, y, z, rgb=None, leaf=0.02, radius=None, umbral=16, seed=1, round_size=1000,
-                 with_points=True, with_count0=False, workspace=None, tuning=None, marked_cap=1 << 16):
+                 with_points=True, with_count0=False, workspace=None, tuning=None, marked_cap=1 << 16,
+                 exact_select=False):
     """Neighbour-bucket decimation (libvg: vg_nbd_decimate; the paper's Alg. 1).
 
     Returns dict: keep_index (int32 view of uint32 input indices of the
@@ -263,7 +268,8 @@ def nbd_decimate(x, y, z, rgb=None, leaf=0.02, radius=None, umbral=16, seed=1, r
     out = vg_nbd_out(_ptr(o["keep_index"]), _ptr(o.get("x")), _ptr(o.get("y")), _ptr(o.get("z")),
                      _ptr(o.get("rgb")), _ptr(o.get("count0")), ctypes.c_void_p(marked.ctypes.data),
                      marked_cap)
-    prm = vg_nbd_params(float(leaf), float(radius), int(umbral), int(round_size), int(seed))
+    prm = vg_nbd_params(float(leaf), float(radius), int(umbral), int(round_size), int(seed),
+                        NBD_EXACT_SELECT if exact_select else 0, 0)
     wsb = int(lib().vg_nbd_workspace_bytes(max(n, 1), int(round_size)))
     if workspace is None or workspace.numel() < wsb:
         workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)

@@ -70,6 +70,22 @@ def test_random_clouds_with_duplicates_and_faces():
         check(g, o, x, y, z, None, trial)
 
 
+@pytest.mark.parametrize("rs", [1, 37, 1000])
+def test_exact_select_gives_the_same_deletions(rs):
+    """The exact select over every marked point (used when the priority window
+    holds too few candidates) against the oracle and the windowed path."""
+    print(f"case nbd exact select, round size {rs}", flush=True)
+    x, y, z, rgb = dg.rgbd_frame(160, 120, seed=31)
+    d = to_dev(x, y, z, rgb.reshape(-1))
+    a = vg.nbd_decimate(*d, leaf=0.05, umbral=20, seed=9, round_size=rs, with_count0=True,
+                        exact_select=True)
+    b = vg.nbd_decimate(*d, leaf=0.05, umbral=20, seed=9, round_size=rs, with_count0=True)
+    torch.cuda.synchronize()
+    o = oracle.nbd_decimate(x, y, z, 0.05, 0.05, 20, 9, rs)
+    check(a, o, x, y, z, rgb, ("exact", rs))
+    check(b, o, x, y, z, rgb, ("window", rs))
+
+
 def test_lattice_closed_form():
     s = 1.0 / 16
     x, y, z = nbd_pins.lattice(12, s)
