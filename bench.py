@@ -234,6 +234,79 @@ def single_cloud_leg(name, cloud, leaf, tuning, dev, reps, oracle_runs):
     return leg
 
 
+def nbd_candidate_checks(x, y, z, leaf):
+    """Point pairs the 27-bucket search examines (host-side accounting): for
+    every valid point, the points of the 27 cells around its own (itself
+    included), on the grid of the voxel filter."""
+    v = np.isfinite(x) & np.isfinite(y) & np.isfinite(z)
+    if not v.any():
+        return 0
+    inv = np.float32(1.0) / np.float32(leaf)
+    k = [np.floor((a[v] - a[v].min()) * inv).astype(np.int64) for a in (x, y, z)]
+    d = [int(kk.max()) + 1 for kk in k]
+    key = k[0] + d[0] * (k[1] + d[1] * k[2])
+    uniq, cnt = np.unique(key, return_counts=True)
+    ux, t = uniq % d[0], uniq // d[0]
+    uy, uz = t % d[1], t // d[1]
+    s = np.zeros(uniq.size, np.int64)
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                nx, ny, nz = ux + dx, uy + dy, uz + dz
+                ok = (nx >= 0) & (nx < d[0]) & (ny >= 0) & (ny < d[1]) & (nz >= 0) & (nz < d[2])
+                nk = nx + d[0] * (ny + d[1] * nz)
+                pos = np.searchsorted(uniq, nk)
+                pos = np.minimum(pos, uniq.size - 1)
+                hit = ok & (uniq[pos] == nk)
+                s += np.where(hit, cnt[pos], 0)
+    return int((cnt * s).sum())
+
+
+def nbd_leg(tuning, dev, reps=5, oracle_runs=1):
+    """The paper's own filter (Alg. 1, neighbour-bucket decimation) on a
+    640x480 frame: leaf and radius 0.02 m (the paper's Table I grid),
+    umbral 16, 1000 points per round.  Whole synchronous calls are timed."""
+    import torch
+
+    from paper_2102_11084_amd import datagen as dg
+    from paper_2102_11084_amd import vg
+    x, y, z, rgb = dg.frame_640x480()
+    n = x.size
+    leaf, umbral, rs, seed = 0.02, 16, 1000, 7
+    d = [torch.from_numpy(a).to(dev) for a in (x, y, z, rgb.reshape(-1))]
+    ws = torch.empty(int(vg.lib().vg_nbd_workspace_bytes(n, rs)), dtype=torch.uint8, device=dev)
+    r = vg.nbd_decimate(*d, leaf=leaf, umbral=umbral, seed=seed, round_size=rs, workspace=ws,
+                        tuning=tuning)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        r = vg.nbd_decimate(*d, leaf=leaf, umbral=umbral, seed=seed, round_size=rs, workspace=ws,
+                            tuning=tuning)
+        ts.append(time.perf_counter() - t0)
+    med = float(np.median(ts))
+    leg = {"workload": "neighbour-bucket decimation (Alg. 1) of a 640x480 RGB-D frame, leaf = radius "
+                       "= 0.02 m, umbral 16, 1000 points per round, seed 7",
+           "points": n, "valid_points": int(np.isfinite(z).sum()), "survivors": int(r["n_keep"]),
+           "rounds": int(r["rounds"]), "marked_first_round": int(r["marked"][0]),
+           "ms_median": round(med * 1e3, 3),
+           "ms_min_max": [round(min(ts) * 1e3, 3), round(max(ts) * 1e3, 3)],
+           "us_per_round": round(med * 1e6 / max(int(r["rounds"]), 1), 2),
+           "mpoints_s": round(n / med / 1e6, 2),
+           "candidate_pairs": nbd_candidate_checks(x, y, z, leaf)}
+    if oracle_runs > 0:
+        import oracle
+        oracle.load()
+        ot = []
+        for _ in range(oracle_runs):
+            c0 = time.perf_counter()
+            o = oracle.nbd_decimate(x, y, z, leaf, leaf, umbral, seed, rs)
+            ot.append(time.perf_counter() - c0)
+        leg["oracle_ms_1core"] = round(float(np.median(ot)) * 1e3, 1)
+        leg["matches_oracle"] = bool(o["rounds"] == r["rounds"] and int(o["keep"].sum()) == r["n_keep"])
+    return leg
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -258,6 +331,9 @@ def main():
                     help="steps of the per-kernel event timing region")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and exit")
+    ap.add_argument("--leg", choices=["nbd"], default=None,
+                    help="only run the named leg (without its oracle timing) and print its JSON; "
+                         "for profiling")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -276,6 +352,9 @@ def main():
 
     dev = torch.device("cuda:0")
     tuning = vg.load_tuning(args.tuning) if os.path.exists(args.tuning) else vg.default_tuning()
+    if args.leg == "nbd":
+        print(json.dumps(nbd_leg(tuning, dev, reps=max(args.steps, 1), oracle_runs=0)), flush=True)
+        return
     if args.exec_mode != "tuned":
         tuning.exec_mode = vg.EXEC_PHASED if args.exec_mode == "phased" else vg.EXEC_PERSISTENT
     for kv in args.set:
@@ -479,6 +558,9 @@ def main():
             log(f"leg: {cfg[-1]['workload']}: {cfg[-1]['mpoints_s']} Mpoints/s")
             del room
             result["legs"]["configs"] = cfg
+            result["legs"]["nbd_decimation"] = nbd_leg(tuning, dev)
+            log(f"leg: decimation: {result['legs']['nbd_decimation']['ms_median']} ms per frame, "
+                f"{result['legs']['nbd_decimation']['rounds']} rounds")
 
     if not args.no_cpu_baseline:
         import oracle

@@ -605,7 +605,8 @@ __global__ __launch_bounds__(kPickBlock) void nbd_pick_kernel(NbdWs w) {
 }
 
 // Every point deleted in the round (one wave each) takes one from the count of
-// each of its neighbours.
+// each of its neighbours.  The wave's lanes run over the 9 ranges as one
+// concatenated list, so a deleted point costs ceil(candidates / 64) steps.
 __global__ __launch_bounds__(kNbdBlock) void nbd_decrement_kernel(NbdWs w) {
   const NbdCtl c = *w.ctl;
   if (c.done) return;
@@ -615,12 +616,24 @@ __global__ __launch_bounds__(kNbdBlock) void nbd_decrement_kernel(NbdWs w) {
     const uint32_t d = w.del[g];
     const float px = w.sx[d], py = w.sy[d], pz = w.sz[d];
     const uint2* rg = w.rng + (size_t)w.scell[d] * 9;
+    uint32_t lo[9], end[9];  // range r covers list positions [end[r-1], end[r])
+    uint32_t total = 0;
+#pragma unroll
     for (int r = 0; r < 9; ++r) {
       const uint2 q = rg[r];
-      for (uint32_t k = q.x + lane; k < q.y; k += 64) {
-        const float d2 = nbd_d2(px, py, pz, w.sx[k], w.sy[k], w.sz[k]);
-        if (k != d && d2 <= c.r2) atomicSub(&w.cnt[k], 1u);
+      lo[r] = q.x;
+      total += q.y - q.x;
+      end[r] = total;
+    }
+    for (uint32_t k = lane; k < total; k += 64) {
+      uint32_t q = 0, before = 0;
+#pragma unroll
+      for (int r = 0; r < 9; ++r) {
+        if (k >= before && k < end[r]) q = lo[r] + (k - before);
+        before = end[r];
       }
+      const float d2 = nbd_d2(px, py, pz, w.sx[q], w.sy[q], w.sz[q]);
+      if (q != d && d2 <= c.r2) atomicSub(&w.cnt[q], 1u);
     }
   }
 }

@@ -110,3 +110,15 @@ def test_step_bytes_by_kernel_by_hand():
     total = sum(bench.algorithmic_bytes(n, nv, p, m) for n, nv, p, m in
                 [(100, 80, 2, 10), (50, 0, 0, 0), (40, 40, 3, 5)])
     assert kb["pipeline"] == total
+
+
+def test_nbd_candidate_checks_by_brute_force():
+    rng = np.random.default_rng(5)
+    p = rng.uniform(0, 0.3, size=(300, 3)).astype(np.float32)
+    p[7, 1] = np.nan
+    x, y, z = p[:, 0].copy(), p[:, 1].copy(), p[:, 2].copy()
+    v = np.isfinite(p).all(1)
+    inv = np.float32(1.0) / np.float32(0.05)
+    k = np.floor((p[v] - p[v].min(0)) * inv).astype(np.int64)
+    exp = int((np.abs(k[:, None, :] - k[None, :, :]) <= 1).all(-1).sum())
+    assert bench.nbd_candidate_checks(x, y, z, 0.05) == exp
