@@ -67,6 +67,9 @@ def _bind(lib):
     lib.vgo_nbd.argtypes = [P, P, P, i64, f32, f32, ctypes.c_uint32, ctypes.c_uint64, i64, P, P, P,
                             i64, P]
     lib.vgo_nbd.restype = c_int
+    lib.vgo_downsample_filtered.argtypes = [P, P, P, P, i64, f32, c_int, P, P, f32, f32,
+                                            ctypes.c_uint32] + [P] * 12
+    lib.vgo_downsample_filtered.restype = c_int
     return lib
 
 
@@ -126,6 +129,43 @@ def downsample(x, y, z, rgb, leaf, key_mode=KEY_LINEAR, lib=None):
     m = np.zeros(1, np.int64)
     st = lib.vgo_downsample(
         _ptr(x), _ptr(y), _ptr(z), _ptr(rgb), n, np.float32(leaf), key_mode,
+        _ptr(out["cx"]), _ptr(out["cy"]), _ptr(out["cz"]), _ptr(out["lx"]), _ptr(out["ly"]),
+        _ptr(out["lz"]), _ptr(out["rgb"]), _ptr(out["count"]), _ptr(out["key"]),
+        _ptr(out["ref_index"]), _ptr(out["point_cell"]), _ptr(m))
+    if st != OK:
+        raise OracleError(st)
+    mm = int(m[0])
+    res = {k: v[:mm] for k, v in out.items() if k != "point_cell"}
+    res["point_cell"] = out["point_cell"][:n]
+    res["m"] = mm
+    return res
+
+
+def downsample_filtered(x, y, z, rgb, leaf, rot=None, trans=None, z_min=-np.inf, z_max=np.inf,
+                        min_points=1, key_mode=KEY_LINEAR, lib=None):
+    """The voxel filter after a rigid transform into the global frame (rot:
+    3x3 row-major, trans: 3; both or neither), a height limit z_min <= z' <=
+    z_max and the removal of cells with fewer than min_points points (see
+    vgo.cpp).  Same result layout as downsample."""
+    lib = lib or load()
+    x, y, z = _f32(x), _f32(y), _f32(z)
+    n = x.size
+    cap = max(n, 1)
+    if rgb is not None:
+        rgb = np.ascontiguousarray(rgb, dtype=np.uint8).reshape(-1)
+    R = None if rot is None else np.ascontiguousarray(rot, dtype=np.float32).reshape(9)
+    T = None if trans is None else np.ascontiguousarray(trans, dtype=np.float32).reshape(3)
+    out = dict(
+        cx=np.zeros(cap), cy=np.zeros(cap), cz=np.zeros(cap),
+        lx=np.zeros(cap), ly=np.zeros(cap), lz=np.zeros(cap),
+        rgb=np.zeros((cap, 3), np.uint8), count=np.zeros(cap, np.uint32),
+        key=np.zeros(cap, np.uint64), ref_index=np.zeros(cap, np.int64),
+        point_cell=np.zeros(cap, np.int32),
+    )
+    m = np.zeros(1, np.int64)
+    st = lib.vgo_downsample_filtered(
+        _ptr(x), _ptr(y), _ptr(z), _ptr(rgb), n, np.float32(leaf), key_mode, _ptr(R), _ptr(T),
+        np.float32(z_min), np.float32(z_max), int(min_points),
         _ptr(out["cx"]), _ptr(out["cy"]), _ptr(out["cz"]), _ptr(out["lx"]), _ptr(out["ly"]),
         _ptr(out["lz"]), _ptr(out["rgb"]), _ptr(out["count"]), _ptr(out["key"]),
         _ptr(out["ref_index"]), _ptr(out["point_cell"]), _ptr(m))

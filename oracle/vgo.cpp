@@ -303,6 +303,98 @@ int vgo_centroids_fixed(const double* x, const double* y, const double* z, int64
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
+// The filter's input contract in the costmap layer (Sec. II-C): the cloud is
+// first brought into the global frame, so that its height can be limited, and
+// the filter should also remove sensor noise.  As read here:
+//   * rigid transform: p'_a = RN32(RN32(RN32(RN32(R[a][0]*x) + RN32(R[a][1]*y))
+//     + RN32(R[a][2]*z)) + t[a]), R row-major, when asked for (else p' = p);
+//   * height limit: a point is kept iff it is valid, p' is finite and
+//     z_min <= p'_z <= z_max; the others are treated as invalid points;
+//   * noise: cells with fewer than min_points points are dropped, the
+//     remaining rows renumbered in key order (their points' point_cell too;
+//     points of dropped cells get -1).
+// The voxel filter itself is vgo_downsample on the transformed, cropped cloud.
+
+extern "C" {
+
+int vgo_downsample_filtered(const float* x, const float* y, const float* z, const uint8_t* rgb,
+                            int64_t n, float leaf, int key_mode, const float* rot,
+                            const float* trans, float z_min, float z_max, uint32_t min_points,
+                            double* cx, double* cy, double* cz, double* lx, double* ly, double* lz,
+                            uint8_t* rgb_out, uint32_t* count, uint64_t* key, int64_t* ref_index,
+                            int32_t* point_cell, int64_t* m) {
+  if (!m) return VGO_ERR_ARG;
+  *m = 0;
+  if (n < 0 || (n > 0 && (!x || !y || !z))) return VGO_ERR_ARG;
+  if (std::isnan(z_min) || std::isnan(z_max) || z_min > z_max) return VGO_ERR_ARG;
+  if (rot || trans) {
+    if (!rot || !trans) return VGO_ERR_ARG;
+    for (int k = 0; k < 9; ++k)
+      if (!std::isfinite(rot[k])) return VGO_ERR_ARG;
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(trans[k])) return VGO_ERR_ARG;
+  }
+  const float nan = std::nanf("");
+  std::vector<float> gx((size_t)std::max<int64_t>(n, 1)), gy(gx.size()), gz(gx.size());
+  for (int64_t i = 0; i < n; ++i) {
+    float p[3] = {x[i], y[i], z[i]};
+    float q[3] = {p[0], p[1], p[2]};
+    if (rot) {
+      for (int a = 0; a < 3; ++a) {
+        float s0 = rot[3 * a + 0] * p[0];
+        float s1 = rot[3 * a + 1] * p[1];
+        float s2 = rot[3 * a + 2] * p[2];
+        float s01 = s0 + s1;
+        float s012 = s01 + s2;
+        q[a] = s012 + trans[a];
+      }
+    }
+    bool keep = point_is_valid(p[0], p[1], p[2]) && point_is_valid(q[0], q[1], q[2]) &&
+                q[2] >= z_min && q[2] <= z_max;
+    gx[i] = keep ? q[0] : nan;
+    gy[i] = keep ? q[1] : nan;
+    gz[i] = keep ? q[2] : nan;
+  }
+  const size_t cap = (size_t)std::max<int64_t>(n, 1);
+  std::vector<double> ax(cap), ay(cap), az(cap), bx(cap), by(cap), bz(cap);
+  std::vector<uint8_t> argb(3 * cap);
+  std::vector<uint32_t> acount(cap);
+  std::vector<uint64_t> akey(cap);
+  std::vector<int64_t> aref(cap);
+  std::vector<int32_t> apc(cap);
+  int64_t am = 0;
+  int st = vgo_downsample(gx.data(), gy.data(), gz.data(), rgb, n, leaf, key_mode, ax.data(),
+                          ay.data(), az.data(), bx.data(), by.data(), bz.data(), argb.data(),
+                          acount.data(), akey.data(), aref.data(), apc.data(), &am);
+  if (st != VGO_OK) return st;
+  // drop the cells with fewer than min_points points
+  std::vector<int64_t> row((size_t)std::max<int64_t>(am, 1), -1);
+  int64_t r = 0;
+  for (int64_t k = 0; k < am; ++k) {
+    if (acount[k] < min_points) continue;
+    row[k] = r;
+    if (cx) cx[r] = ax[k];
+    if (cy) cy[r] = ay[k];
+    if (cz) cz[r] = az[k];
+    if (lx) lx[r] = bx[k];
+    if (ly) ly[r] = by[k];
+    if (lz) lz[r] = bz[k];
+    if (rgb_out)
+      for (int a = 0; a < 3; ++a) rgb_out[3 * r + a] = argb[3 * k + a];
+    if (count) count[r] = acount[k];
+    if (key) key[r] = akey[k];
+    if (ref_index) ref_index[r] = aref[k];
+    ++r;
+  }
+  if (point_cell)
+    for (int64_t i = 0; i < n; ++i) point_cell[i] = apc[i] < 0 ? -1 : (int32_t)row[apc[i]];
+  *m = r;
+  return VGO_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
 // Neighbour-bucket decimation (arXiv 2102.11084, Sec. II-C, Alg. 1).
 //
 // What the paper's own GPU filter computes, as read here:

@@ -8,6 +8,7 @@ import os
 
 import pytest
 
+import filter_pins
 import nbd_pins
 import oracle
 import oracle_pins as pins
@@ -51,6 +52,16 @@ MUTANTS = {
     "nbd_counts_itself": ("if (q == i) continue;\n            if (dist2", "if (dist2"),
     "nbd_dist_axis_slip": ("float dz = bz - az;", "float dz = by - ay;"),
     "nbd_counts_deleted": ("for (int64_t q : nbr[i]) cnt += present[q];", "for (int64_t q : nbr[i]) cnt += 1;"),
+    # transform, height limit, minimum points per cell
+    "filter_trans_sign": ("q[a] = s012 + trans[a];", "q[a] = s012 - trans[a];"),
+    "filter_rot_column_slip": ("float s1 = rot[3 * a + 1] * p[1];", "float s1 = rot[3 * a + 1] * p[2];"),
+    "filter_rot_transposed_row": ("float s0 = rot[3 * a + 0] * p[0];", "float s0 = rot[a] * p[0];"),
+    "filter_limit_exclusive": ("q[2] >= z_min && q[2] <= z_max", "q[2] > z_min && q[2] <= z_max"),
+    "filter_limit_on_y": ("q[2] >= z_min && q[2] <= z_max", "q[1] >= z_min && q[1] <= z_max"),
+    "filter_limit_before_transform": ("q[2] >= z_min && q[2] <= z_max", "p[2] >= z_min && p[2] <= z_max"),
+    "filter_min_points_strict": ("if (acount[k] < min_points) continue;", "if (acount[k] <= min_points) continue;"),
+    "filter_rows_not_renumbered": ("point_cell[i] = apc[i] < 0 ? -1 : (int32_t)row[apc[i]];",
+                                   "point_cell[i] = apc[i];"),
 }
 
 
@@ -63,7 +74,7 @@ def test_mutant_is_caught(name, tmp_path):
     mpath.write_text(src.replace(old, new))
     lib = oracle.load(oracle.build(str(mpath), str(tmp_path / "libmutant.so")))
     caught = []
-    for pin in pins.ALL_PINS + nbd_pins.ALL_NBD_PINS:
+    for pin in pins.ALL_PINS + nbd_pins.ALL_NBD_PINS + filter_pins.ALL_FILTER_PINS:
         try:
             pin(lib)
         except Exception as err:  # any failure of a pin counts as catching the mutant
