@@ -200,6 +200,47 @@ vg_status vg_downsample_batched(vg_batch_plan *plan, const vg_points *p,
                                 vg_cells *out, int64_t *out_offsets, int32_t *frame_status,
                                 void *stream);
 
+/* ---- the filter's input contract: global frame, height limit, noise ----
+ * Sec. II-C: the costmap layer hands the filter a cloud already transformed
+ * into the global frame, so that its height can be limited for the
+ * navigation stack's projection; the filter is also meant to remove the
+ * depth sensor's noise.  Per cloud (frame):
+ *   - if flags has VG_FILTER_TRANSFORM, every point is moved first:
+ *     p'_a = RN32(RN32(RN32(RN32(rot[3a] x) + RN32(rot[3a+1] y)) + RN32(rot[3a+2] z))
+ *            + trans[a]) in binary32 (rot row-major; applied as given);
+ *   - a point is kept iff it is valid, p' is finite and
+ *     z_min <= p'_z <= z_max (both inclusive; -INFINITY / INFINITY: no limit);
+ *     the others are invalid points (point_cell -1);
+ *   - the voxel filter runs on the kept points p' (outputs in that frame);
+ *   - cells with fewer than min_points points are dropped (0 or 1: none) and
+ *     the remaining rows renumbered in key order; their points' point_cell
+ *     follows, points of dropped cells get -1.
+ * The transform and height limit are applied by the bbox pass, which writes
+ * the moved points once for the later passes; the sparse cells are removed by
+ * a short pass over the output rows, launched only when asked for. */
+typedef struct vg_filter {
+  float rot[9];          /* row-major, used with VG_FILTER_TRANSFORM */
+  float trans[3];
+  float z_min, z_max;    /* not NaN, z_min <= z_max */
+  uint32_t min_points;
+  uint32_t flags;        /* VG_FILTER_* bits; others must be 0 */
+} vg_filter;
+#define VG_FILTER_TRANSFORM 1u
+
+/* vg_downsample_ex on the filtered cloud (f: one filter).  VG_ERR_ARG for a
+ * NULL or malformed filter (NaN or crossed limits, non-finite rot / trans
+ * with VG_FILTER_TRANSFORM, unknown flags). */
+vg_status vg_downsample_filtered(const vg_points *p, int64_t n, float leaf, const vg_filter *f,
+                                 vg_cells *out, int64_t *m, const vg_options *o);
+
+/* vg_downsample_batched with a filter per frame (filters: host [B]).  The
+ * plan's graph gains the sparse-cell pass on the first call that needs it. */
+vg_status vg_downsample_batched_filtered(vg_batch_plan *plan, const vg_points *p,
+                                         const int64_t *frame_offsets, const float *leaf,
+                                         const vg_filter *filters, int B, vg_cells *out,
+                                         int64_t *out_offsets, int32_t *frame_status,
+                                         void *stream);
+
 /* Kernels of the pipeline, as reported by vg_batch_plan_kernel_times. */
 typedef enum vg_kernel_kind {
   VG_KERNEL_INIT = 0,     /* state reset */
@@ -315,7 +356,7 @@ vg_status vg_nbd_decimate(const vg_points *p, int64_t n, const vg_nbd_params *pr
  * state it needs at its start: calls must be ordered (one stream, or
  * synchronised); calls that overlap on one GPU race and give wrong results. */
 #define VG_NOALLOC_MAX_POINTS 1048576
-#define VG_NOALLOC_SCRATCH_BYTES (48u << 20)
+#define VG_NOALLOC_SCRATCH_BYTES (64u << 20)
 vg_status vg_downsample_noalloc(const vg_points *p, int64_t n, float leaf, vg_key_mode key_mode,
                                 vg_cells *out, int64_t *d_m, int32_t *d_status, void *stream);
 

@@ -12,6 +12,7 @@
 #include "../../include/vg.h"
 #include "vg_pipeline.hpp"
 #include "vg_nbd.hpp"
+#include "vg_sparse.hpp"
 
 namespace {
 
@@ -111,9 +112,9 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
   int64_t capN;
   int capB, capNTb, capNTs, capNTr, slots, R;
-  size_t hdr, io, fd, tpb, tps, tpr, ilv_s, ilv_perm, staged;  // staged: copied from the host
+  size_t hdr, io, fd, tpb, tps, tpr, ilv_s, ilv_perm, xf, staged;  // staged: copied from the host
   size_t tinfo, ctl, fs, hist, sdesc, rdesc, fflag, frag, pend, lo0, lo1, hi0, hi1, id0, id1, rec,
-      outoff, fstat;
+      tx, ty, tz, rflag, rpos, bsum, outoff, fstat;
   size_t total;
 };
 
@@ -137,6 +138,7 @@ Layout make_layout(int64_t capN, int capB, const Variant& v) {
   L.tpr = o;  o = align_up(o + 4 * (size_t)(L.capB + 1));
   L.ilv_s = o; o = align_up(o + 4 * (size_t)(kIlvMaxRounds + 1));
   L.ilv_perm = o; o = align_up(o + 4 * (size_t)kIlvMaxFrames);
+  L.xf = o;   o = align_up(o + sizeof(FrameXf) * L.capB);
   L.staged = o;
   L.tinfo = o; o = align_up(o + 8 * ((size_t)L.capNTb + L.capNTs + L.capNTr));
   L.ctl = o;  o = align_up(o + sizeof(Ctl));
@@ -155,6 +157,12 @@ Layout make_layout(int64_t capN, int capB, const Variant& v) {
   L.id0 = o; o = align_up(o + nb);
   L.id1 = o; o = align_up(o + nb);
   L.rec = o; o = align_up(o + 16 * (size_t)L.capN);
+  L.tx = o; o = align_up(o + nb);
+  L.ty = o; o = align_up(o + nb);
+  L.tz = o; o = align_up(o + nb);
+  L.rflag = o; o = align_up(o + nb + 4);
+  L.rpos = o; o = align_up(o + nb + 4);
+  L.bsum = o; o = align_up(o + 4 * ((size_t)(L.capN + kScanTile - 1) / kScanTile + 1));
   L.outoff = o; o = align_up(o + 8 * (size_t)(L.capB + 1));
   L.fstat = o; o = align_up(o + 4 * (size_t)L.capB);
   L.total = o;
@@ -188,6 +196,13 @@ Ws carve(const Layout& L, void* base) {
   w.idx[0] = reinterpret_cast<uint32_t*>(b + L.id0);
   w.idx[1] = reinterpret_cast<uint32_t*>(b + L.id1);
   w.rec = reinterpret_cast<float4*>(b + L.rec);
+  w.xf = reinterpret_cast<FrameXf*>(b + L.xf);
+  w.tx = reinterpret_cast<float*>(b + L.tx);
+  w.ty = reinterpret_cast<float*>(b + L.ty);
+  w.tz = reinterpret_cast<float*>(b + L.tz);
+  w.rflag = reinterpret_cast<uint32_t*>(b + L.rflag);
+  w.rpos = reinterpret_cast<uint32_t*>(b + L.rpos);
+  w.bsum = reinterpret_cast<uint32_t*>(b + L.bsum);
   w.capB = L.capB;
   w.capNTb = L.capNTb;
   w.capNTs = L.capNTs;
@@ -229,10 +244,27 @@ bool cells_consistent(const vg_cells* c) {
 
 // Fills the staged region (header, io, frame descriptors, tile prefixes) on
 // the host.  Returns false if some frame is too large.
+// Checks the per-frame filters (NULL: none).
+bool filters_ok(const vg_filter* f, int B) {
+  if (!f) return true;
+  for (int b = 0; b < B; ++b) {
+    if (std::isnan(f[b].z_min) || std::isnan(f[b].z_max) || f[b].z_min > f[b].z_max) return false;
+    if (f[b].flags & ~(uint32_t)VG_FILTER_TRANSFORM) return false;
+    if (f[b].flags & VG_FILTER_TRANSFORM) {
+      for (int k = 0; k < 9; ++k)
+        if (!std::isfinite(f[b].rot[k])) return false;
+      for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(f[b].trans[k])) return false;
+    }
+  }
+  return true;
+}
+
 bool fill_staging(char* st, const Layout& L, const Variant& v, const vg_points* p,
                   const int64_t* offs, const float* leaves, const float* invs, int B,
                   const vg_cells* out, int64_t* out_offsets, int32_t* frame_status, int key_mode,
-                  int fail_waits, CallHdr* hdr_out) {
+                  int fail_waits, CallHdr* hdr_out, const Ws& ws,
+                  const vg_filter* filters = nullptr) {
   CallHdr hdr;
   std::memset(&hdr, 0, sizeof hdr);
   hdr.B = B;
@@ -260,6 +292,40 @@ bool fill_staging(char* st, const Layout& L, const Variant& v, const vg_points* 
   io.lz = out->lz;
   io.out_offsets = out_offsets;
   io.frame_status = frame_status;
+  // filters: the bbox pass writes the point view when some frame transforms or
+  // limits its height; sparse cells go after the pipeline when some frame asks
+  io.vx = p->x;
+  io.vy = p->y;
+  io.vz = p->z;
+  if (filters) {
+    FrameXf* xf = reinterpret_cast<FrameXf*>(st + L.xf);
+    for (int b = 0; b < B; ++b) {
+      const vg_filter& f = filters[b];
+      FrameXf& x = xf[b];
+      std::memset(&x, 0, sizeof x);
+      if (f.flags & VG_FILTER_TRANSFORM) {
+        x.on |= kXfRotate;
+        for (int k = 0; k < 9; ++k) x.r[k] = f.rot[k];
+        for (int k = 0; k < 3; ++k) x.t[k] = f.trans[k];
+      }
+      x.zlo = f.z_min;
+      x.zhi = f.z_max;
+      if (!(f.z_min == -INFINITY && f.z_max == INFINITY)) x.on |= kXfLimit;
+      x.minp = f.min_points;
+      if (x.on) hdr.filt |= kFiltView;
+      if (f.min_points > 1) hdr.filt |= kFiltMinPts;
+    }
+    if (hdr.filt & kFiltView) {
+      io.vx = ws.tx;
+      io.vy = ws.ty;
+      io.vz = ws.tz;
+    }
+    if ((hdr.filt & kFiltMinPts) && !io.count) {
+      io.count = ws.rpos;  // counts for the sparse-cell pass only, not an output
+      hdr.want |= kOutCount;
+      hdr.filt |= kFiltCountInternal;
+    }
+  }
   FrameDesc* fd = reinterpret_cast<FrameDesc*>(st + L.fd);
   uint32_t* tpb = reinterpret_cast<uint32_t*>(st + L.tpb);
   uint32_t* tps = reinterpret_cast<uint32_t*>(st + L.tps);
@@ -356,18 +422,36 @@ vg_kernel_kind kind_of_phase(const Variant& v, int lo, int hi) {
 // Enqueues: staged copy, state reset, pipeline.  All launches have fixed
 // shapes (no per-call kernel arguments), so the sequence can be captured.
 vg_status enqueue_kernels(const Variant& v, const Ws& ws, int exec_mode, int cus, int bpc,
-                          hipStream_t s, LaunchTimer* tm = nullptr);
+                          hipStream_t s, LaunchTimer* tm = nullptr, bool sparse = false);
 
 vg_status enqueue(const Variant& v, const Layout& L, const Ws& ws, const char* staging,
-                  int exec_mode, int cus, int bpc, hipStream_t s, LaunchTimer* tm = nullptr) {
+                  int exec_mode, int cus, int bpc, hipStream_t s, LaunchTimer* tm = nullptr,
+                  bool sparse = false) {
   if (hipMemcpyAsync(ws.hdr, staging, L.staged, hipMemcpyHostToDevice, s) != hipSuccess)
     return VG_ERR_DEVICE;
-  return enqueue_kernels(v, ws, exec_mode, cus, bpc, s, tm);
+  return enqueue_kernels(v, ws, exec_mode, cus, bpc, s, tm, sparse);
+}
+
+// The sparse-cell pass (launched when a call asks for a minimum of points per
+// cell; its kernels read the call header and exit at once otherwise).
+void enqueue_sparse(const Ws& ws, hipStream_t s) {
+  const int64_t N = ws.capN;
+  const int g = (int)std::max<int64_t>(1, std::min<int64_t>((N + kSparseBlock - 1) / kSparseBlock, 4096));
+  const int nb = (int)((N + kScanTile - 1) / kScanTile);
+  hipLaunchKernelGGL(vg_sparse_flag_kernel, dim3(g), dim3(kSparseBlock), 0, s, ws);
+  hipLaunchKernelGGL(vg_scan_tiles, dim3(nb), dim3(kScanBlock), 0, s, ws.rflag, &ws.ctl->rows,
+                     ws.bsum);
+  hipLaunchKernelGGL(vg_scan_top, dim3(1), dim3(1024), 0, s, &ws.ctl->rows, ws.bsum,
+                     &ws.ctl->rows_kept);
+  hipLaunchKernelGGL(vg_scan_apply, dim3(nb), dim3(kScanBlock), 0, s, ws.rflag, &ws.ctl->rows,
+                     ws.bsum, ws.rpos, nullptr, &ws.ctl->rows_kept);
+  hipLaunchKernelGGL(vg_sparse_gather_kernel, dim3(g), dim3(kSparseBlock), 0, s, ws);
+  hipLaunchKernelGGL(vg_sparse_scatter_kernel, dim3(g), dim3(kSparseBlock), 0, s, ws);
 }
 
 // State reset, pipeline, status (the staged region must already be on its way).
 vg_status enqueue_kernels(const Variant& v, const Ws& ws, int exec_mode, int cus, int bpc,
-                          hipStream_t s, LaunchTimer* tm) {
+                          hipStream_t s, LaunchTimer* tm, bool sparse) {
   if (tm) tm->n = 0;
   auto mark = [&](int k, int which) {
     if (tm && tm->n < LaunchTimer::kMax) {
@@ -396,6 +480,7 @@ vg_status enqueue_kernels(const Variant& v, const Ws& ws, int exec_mode, int cus
       ph = hi;
     }
   }
+  if (sparse) enqueue_sparse(ws, s);
   hipLaunchKernelGGL(vg_status_kernel, dim3(1), dim3(256), 0, s, ws);
   if (hipGetLastError() != hipSuccess) return VG_ERR_DEVICE;
   return VG_OK;
@@ -461,10 +546,16 @@ size_t vg_workspace_bytes(int64_t n_total, int n_frames, const vg_tuning* t) {
   return make_layout(n_total, n_frames, *v).total;
 }
 
-vg_status vg_downsample_ex(const vg_points* p, int64_t n, float leaf, vg_cells* out, int64_t* m,
-                           const vg_options* o) {
+}  // extern "C"
+
+namespace {
+
+// One cloud, optionally filtered (filter NULL: none).
+vg_status downsample_one(const vg_points* p, int64_t n, float leaf, const vg_filter* filter,
+                         vg_cells* out, int64_t* m, const vg_options* o) {
   if (m) *m = 0;
   if (!p || !out || !m || !o) return VG_ERR_ARG;
+  if (!filters_ok(filter, 1)) return VG_ERR_ARG;
   if (n < 0 || n > kMaxFramePoints) return VG_ERR_ARG;
   if (o->key_mode != VG_KEY_LINEAR && o->key_mode != VG_KEY_MORTON) return VG_ERR_ARG;
   if (n > 0 && (!p->x || !p->y || !p->z)) return VG_ERR_ARG;
@@ -498,12 +589,13 @@ vg_status vg_downsample_ex(const vg_points* p, int64_t n, float leaf, vg_cells* 
   int32_t* d_st = reinterpret_cast<int32_t*>(static_cast<char*>(base) + L.fstat);
   vg_status rc = VG_OK;
   bool enqueued = false;
-  if (!fill_staging(st, L, *v, p, offs, &leaf, &inv, 1, out, d_off, d_st, o->key_mode, 0, &hdr)) {
+  if (!fill_staging(st, L, *v, p, offs, &leaf, &inv, 1, out, d_off, d_st, o->key_mode, 0, &hdr, ws,
+                    filter)) {
     rc = VG_ERR_ARG;
   } else {
     const int mode = o->tuning ? o->tuning->exec_mode : kDefaultTuning.exec_mode;
     enqueued = true;
-    rc = enqueue(*v, L, ws, st, mode, cus, bpc, s);
+    rc = enqueue(*v, L, ws, st, mode, cus, bpc, s, nullptr, (hdr.filt & kFiltMinPts) != 0);
   }
   Readback* rb = reinterpret_cast<Readback*>(st + L.staged);
   if (rc == VG_OK) {
@@ -532,6 +624,22 @@ vg_status vg_downsample_ex(const vg_points* p, int64_t n, float leaf, vg_cells* 
   if (owned || (enqueued && rc != VG_OK)) (void)hipStreamSynchronize(s);
   if (owned) (void)hipFree(base);
   return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+vg_status vg_downsample_ex(const vg_points* p, int64_t n, float leaf, vg_cells* out, int64_t* m,
+                           const vg_options* o) {
+  return downsample_one(p, n, leaf, nullptr, out, m, o);
+}
+
+vg_status vg_downsample_filtered(const vg_points* p, int64_t n, float leaf, const vg_filter* f,
+                                 vg_cells* out, int64_t* m, const vg_options* o) {
+  if (m) *m = 0;
+  if (!f) return VG_ERR_ARG;
+  return downsample_one(p, n, leaf, f, out, m, o);
 }
 
 vg_status vg_downsample(const vg_points* p, int64_t n, float leaf, vg_cells* out, int64_t* m) {
@@ -573,7 +681,7 @@ NbdLayout make_nbd_layout(size_t o, int64_t n, int64_t round_size) {
   NbdLayout L;
   const size_t N = (size_t)std::max<int64_t>(n, 1);
   const size_t K = (size_t)std::max<int64_t>(1, std::min<int64_t>(round_size, (int64_t)N));
-  L.scan_blocks = (int)((N + kNbdScanTile - 1) / kNbdScanTile);
+  L.scan_blocks = (int)((N + kScanTile - 1) / kScanTile);
   L.log_cap = (uint32_t)std::min<int64_t>((int64_t)N / (int64_t)K + 2, (int64_t)1 << 24);
   o = align_up(o);
   L.ckey = o;   o = align_up(o + 8 * N);
@@ -718,7 +826,7 @@ vg_status vg_nbd_decimate(const vg_points* p, int64_t n, const vg_nbd_params* pr
   vg_status rc = VG_OK;
   bool enqueued = false;
   if (!fill_staging(st, L, *v, &pin, offs, &leaf, &inv, 1, &cells, d_off, d_st, VG_KEY_LINEAR, 0,
-                    &hdr)) {
+                    &hdr, ws)) {
     rc = VG_ERR_ARG;
   } else {
     enqueued = true;
@@ -733,10 +841,10 @@ vg_status vg_nbd_decimate(const vg_points* p, int64_t n, const vg_nbd_params* pr
     hipLaunchKernelGGL(nbd_setup_kernel, dim3(grid_for(n, kNbdBlock, 1024)), dim3(kNbdBlock), 0, s,
                        ws, w, prm->umbral, (uint32_t)prm->round_size, prm->seed, r2, NL.log_cap,
                        (prm->flags & VG_NBD_EXACT_SELECT) ? 1u : 0u);
-    hipLaunchKernelGGL(nbd_scan_tiles, dim3(nb), dim3(kNbdBlock), 0, s, w.ccount, &w.ctl->m, w.bsum);
-    hipLaunchKernelGGL(nbd_scan_top, dim3(1), dim3(1024), 0, s, &w.ctl->m, w.bsum,
+    hipLaunchKernelGGL(vg_scan_tiles, dim3(nb), dim3(kScanBlock), 0, s, w.ccount, &w.ctl->m, w.bsum);
+    hipLaunchKernelGGL(vg_scan_top, dim3(1), dim3(1024), 0, s, &w.ctl->m, w.bsum,
                        &w.ctl->scan_total);
-    hipLaunchKernelGGL(nbd_scan_apply, dim3(nb), dim3(kNbdBlock), 0, s, w.ccount, &w.ctl->m,
+    hipLaunchKernelGGL(vg_scan_apply, dim3(nb), dim3(kScanBlock), 0, s, w.ccount, &w.ctl->m,
                        w.bsum, w.seg, w.cursor, &w.ctl->scan_total);
     const int gp = grid_for(n, kNbdBlock, 8192);
     hipLaunchKernelGGL(nbd_scatter_kernel, dim3(gp), dim3(kNbdBlock), 0, s, w);
@@ -776,10 +884,10 @@ vg_status vg_nbd_decimate(const vg_points* p, int64_t n, const vg_nbd_params* pr
     // 4. survivors in input order
     hipLaunchKernelGGL(nbd_keep_kernel, dim3(grid_for(n, kNbdBlock, 8192)), dim3(kNbdBlock), 0, s, w);
     const int nb = NL.scan_blocks;
-    hipLaunchKernelGGL(nbd_scan_tiles, dim3(nb), dim3(kNbdBlock), 0, s, w.keep, &w.ctl->n_in, w.bsum);
-    hipLaunchKernelGGL(nbd_scan_top, dim3(1), dim3(1024), 0, s, &w.ctl->n_in, w.bsum,
+    hipLaunchKernelGGL(vg_scan_tiles, dim3(nb), dim3(kScanBlock), 0, s, w.keep, &w.ctl->n_in, w.bsum);
+    hipLaunchKernelGGL(vg_scan_top, dim3(1), dim3(1024), 0, s, &w.ctl->n_in, w.bsum,
                        &w.ctl->scan_total);
-    hipLaunchKernelGGL(nbd_scan_apply, dim3(nb), dim3(kNbdBlock), 0, s, w.keep, &w.ctl->n_in,
+    hipLaunchKernelGGL(vg_scan_apply, dim3(nb), dim3(kScanBlock), 0, s, w.keep, &w.ctl->n_in,
                        w.bsum, w.kpos, nullptr, &w.ctl->scan_total);
     hipLaunchKernelGGL(nbd_emit_kernel, dim3(grid_for(n, kNbdBlock, 8192)), dim3(kNbdBlock), 0, s, w);
     const bool ok =
@@ -868,7 +976,7 @@ vg_status vg_downsample_noalloc(const vg_points* p, int64_t n, float leaf, vg_ke
   int64_t* w_off = reinterpret_cast<int64_t*>(static_cast<char*>(base) + L.outoff);
   int32_t* w_st = reinterpret_cast<int32_t*>(static_cast<char*>(base) + L.fstat);
   CallHdr hdr;
-  if (!fill_staging(st, L, *v, p, offs, &leaf, &inv, 1, out, w_off, w_st, key_mode, 0, &hdr))
+  if (!fill_staging(st, L, *v, p, offs, &leaf, &inv, 1, out, w_off, w_st, key_mode, 0, &hdr, ws))
     return VG_ERR_ARG;
   StageArgs a;
   std::memcpy(&a.hdr, st + L.hdr, sizeof a.hdr);
@@ -909,6 +1017,7 @@ struct vg_batch_plan {
   hipGraphExec_t gexec;
   LaunchTimer* timer;  // non-null while timing is on
   int fail_waits;      // test support: calls start with the time-out flag raised
+  bool graph_sparse;   // the captured graph holds the sparse-cell pass
 };
 
 extern "C" {
@@ -940,6 +1049,7 @@ vg_status vg_batch_plan_create(int max_frames, int64_t max_total_points, vg_key_
   P->done = nullptr;
   P->timer = nullptr;
   P->fail_waits = 0;
+  P->graph_sparse = false;
   vg_status rc = VG_OK;
   if (hipGetDevice(&P->device) != hipSuccess) rc = VG_ERR_DEVICE;
   if (rc == VG_OK && (P->cus = device_cus(P->device)) <= 0) rc = VG_ERR_DEVICE;
@@ -1018,9 +1128,13 @@ vg_status vg_batch_plan_kernel_times(vg_batch_plan* plan, int* kinds, float* ms,
   return VG_OK;
 }
 
-vg_status vg_downsample_batched(vg_batch_plan* P, const vg_points* p, const int64_t* offs,
-                                const float* leaf, int B, vg_cells* out, int64_t* out_offsets,
-                                int32_t* frame_status, void* stream) {
+}  // extern "C"
+
+namespace {
+
+vg_status downsample_batch(vg_batch_plan* P, const vg_points* p, const int64_t* offs,
+                           const float* leaf, const vg_filter* filters, int B, vg_cells* out,
+                           int64_t* out_offsets, int32_t* frame_status, void* stream) {
   if (!P || !p || !offs || !leaf || !out || !out_offsets || !frame_status) return VG_ERR_ARG;
   if (B < 1 || B > P->max_frames) return VG_ERR_ARG;
   if (offs[0] != 0) return VG_ERR_ARG;
@@ -1029,6 +1143,7 @@ vg_status vg_downsample_batched(vg_batch_plan* P, const vg_points* p, const int6
   if (offs[B] > P->max_points) return VG_ERR_ARG;
   if (offs[B] > 0 && (!p->x || !p->y || !p->z)) return VG_ERR_ARG;
   if (!cells_consistent(out)) return VG_ERR_ARG;
+  if (!filters_ok(filters, B)) return VG_ERR_ARG;
   for (int b = 0; b < B; ++b)
     if (!leaf_inverse(leaf[b], &P->invs[b])) return VG_ERR_LEAF;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1038,10 +1153,19 @@ vg_status vg_downsample_batched(vg_batch_plan* P, const vg_points* p, const int6
   }
   CallHdr hdr;
   if (!fill_staging(P->staging, P->L, *P->v, p, offs, leaf, P->invs, B, out, out_offsets,
-                    frame_status, P->key_mode, P->fail_waits, &hdr))
+                    frame_status, P->key_mode, P->fail_waits, &hdr, P->ws, filters))
     return VG_ERR_ARG;
+  const bool sparse = (hdr.filt & kFiltMinPts) != 0;
   vg_status rc = VG_OK;
   if (P->use_graph && !P->timer) {
+    // the graph holds the sparse-cell pass once a call has needed it (its
+    // kernels exit at once for calls that do not)
+    if (P->gexec && sparse && !P->graph_sparse) {
+      (void)hipGraphExecDestroy(P->gexec);
+      (void)hipGraphDestroy(P->graph);
+      P->gexec = nullptr;
+      P->graph = nullptr;
+    }
     if (!P->gexec) {
       hipStream_t cs;
       if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return VG_ERR_DEVICE;
@@ -1050,7 +1174,7 @@ vg_status vg_downsample_batched(vg_batch_plan* P, const vg_points* p, const int6
         return VG_ERR_DEVICE;
       }
       rc = enqueue(*P->v, P->L, P->ws, P->staging, P->tuning.exec_mode, P->cus,
-                   P->tuning.blocks_per_cu, cs);
+                   P->tuning.blocks_per_cu, cs, nullptr, sparse);
       hipGraph_t g = nullptr;
       const bool ok = hipStreamEndCapture(cs, &g) == hipSuccess && rc == VG_OK &&
                       hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0) == hipSuccess;
@@ -1061,14 +1185,34 @@ vg_status vg_downsample_batched(vg_batch_plan* P, const vg_points* p, const int6
         return VG_ERR_DEVICE;
       }
       P->graph = g;
+      P->graph_sparse = sparse;
     }
     if (hipGraphLaunch(P->gexec, s) != hipSuccess) rc = VG_ERR_DEVICE;
   } else {
     rc = enqueue(*P->v, P->L, P->ws, P->staging, P->tuning.exec_mode, P->cus,
-                 P->tuning.blocks_per_cu, s, P->timer);
+                 P->tuning.blocks_per_cu, s, P->timer, sparse);
   }
   if (hipEventRecord(P->done, s) == hipSuccess) P->pending = true;
   return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+vg_status vg_downsample_batched(vg_batch_plan* P, const vg_points* p, const int64_t* offs,
+                                const float* leaf, int B, vg_cells* out, int64_t* out_offsets,
+                                int32_t* frame_status, void* stream) {
+  return downsample_batch(P, p, offs, leaf, nullptr, B, out, out_offsets, frame_status, stream);
+}
+
+vg_status vg_downsample_batched_filtered(vg_batch_plan* P, const vg_points* p,
+                                         const int64_t* offs, const float* leaf,
+                                         const vg_filter* filters, int B, vg_cells* out,
+                                         int64_t* out_offsets, int32_t* frame_status,
+                                         void* stream) {
+  if (!filters) return VG_ERR_ARG;
+  return downsample_batch(P, p, offs, leaf, filters, B, out, out_offsets, frame_status, stream);
 }
 
 vg_status vg_batch_plan_destroy(vg_batch_plan* P) {

@@ -38,7 +38,23 @@ struct CallHdr {
   int32_t ilv_rounds;   // > 0: radix-pass tiles are taken round-robin over frames
   int32_t fail_waits;   // non-zero: the call starts with the time-out flag raised (tests of
                         // the error path: every kernel then exits without touching outputs)
+  uint32_t filt;        // kFiltView: the bbox pass writes the point view (transform / height
+                        // limit of some frame); kFiltMinPts: sparse cells are dropped after
+  uint32_t pad2;
 };
+
+enum : uint32_t { kFiltView = 1, kFiltMinPts = 2, kFiltCountInternal = 4 };
+
+// Per-frame input filter (the global-frame transform and height limit that
+// the filter's input contract asks for, and the removal of sparse cells).
+struct FrameXf {
+  float r[9];       // rotation, row-major (applied when on & kXfRotate)
+  float t[3];       // translation
+  float zlo, zhi;   // height limit on the transformed z, inclusive
+  uint32_t on;      // kXfRotate | kXfLimit
+  uint32_t minp;    // cells with fewer points are dropped (<= 1: none)
+};
+enum : uint32_t { kXfRotate = 1, kXfLimit = 2 };
 
 // Round-robin order of the radix-pass tiles: round j holds tile j of every
 // frame with more than j sort tiles, frames by descending tile count.  Each
@@ -109,7 +125,9 @@ struct Ctl {
   uint32_t max_passes;       // max radix passes over the frames of the call
   uint32_t hist_tiles_done;  // big tiles (all frames) whose histogram is done
   uint32_t red_tiles_done;   // reduce tiles (all frames) done
-  uint32_t pad[12];
+  uint32_t rows;             // rows of the call (for the sparse-cell pass)
+  uint32_t rows_kept;        // rows left by the sparse-cell pass
+  uint32_t pad[10];
 };
 
 struct Io;
@@ -136,6 +154,13 @@ struct Ws {
   uint32_t* hi[2];      // [N]
   uint32_t* idx[2];     // [N]
   float4* rec;          // [N] x, y, z and packed rgb of every point, written by the bbox pass
+  FrameXf* xf;          // [B] per-frame filters (staged)
+  float* tx;            // [N] the point view after transform and height limit
+  float* ty;
+  float* tz;
+  uint32_t* rflag;      // [N + 1] rows kept by the sparse-cell pass
+  uint32_t* rpos;       // [N + 1] their new rows (exclusive prefix)
+  uint32_t* bsum;       // [scan tiles + 1]
   Io* io;               // inputs/outputs of the call (copied from the host)
   // capacities the workspace was carved for
   int32_t capB, capNTb, capNTs, capNTr, slots, R;
@@ -149,6 +174,9 @@ struct Io {
   const float* x;
   const float* y;
   const float* z;
+  const float* vx;       // the points as every phase after the bbox pass sees them: x, y, z,
+  const float* vy;       // or the transformed, height-limited copy the bbox pass writes
+  const float* vz;
   const uint8_t* rgb;
   float* cx;
   float* cy;

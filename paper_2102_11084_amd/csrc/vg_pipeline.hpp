@@ -538,6 +538,7 @@ using gptr = __attribute__((address_space(1))) T*;
 
 struct GIo {
   gptr<const float> x, y, z;
+  gptr<const float> vx, vy, vz;  // the point view of the phases after the bbox pass
   gptr<const uint8_t> rgb;
   gptr<float> cx, cy, cz;
   gptr<uint8_t> crgb;
@@ -555,6 +556,9 @@ __device__ __forceinline__ GIo global_view(const Io& o) {
   g.x = (gptr<const float>)o.x;
   g.y = (gptr<const float>)o.y;
   g.z = (gptr<const float>)o.z;
+  g.vx = (gptr<const float>)o.vx;
+  g.vy = (gptr<const float>)o.vy;
+  g.vz = (gptr<const float>)o.vz;
   g.rgb = (gptr<const uint8_t>)o.rgb;
   g.cx = (gptr<float>)o.cx;
   g.cy = (gptr<float>)o.cy;
@@ -580,15 +584,17 @@ struct Pts {
   uint32_t c[HB];  // packed rgb (bbox tiles only)
 };
 
-template <class C, int HB, bool RGB = true>
+// VIEW: read the point view (the phases after the bbox pass) instead of the
+// input as given (the bbox pass).
+template <class C, int HB, bool RGB = true, bool VIEW = false>
 __device__ __forceinline__ void load_pts(const GIo& io, Pts<HB>& p, int64_t g0, int64_t last,
                                          bool with_rgb) {
 #pragma unroll
   for (int u = 0; u < HB; ++u) {
     const int64_t g = min(g0 + u * C::BLOCK + (int)threadIdx.x, last);
-    p.x[u] = io.x[g];
-    p.y[u] = io.y[g];
-    p.z[u] = io.z[g];
+    p.x[u] = VIEW ? io.vx[g] : io.x[g];
+    p.y[u] = VIEW ? io.vy[g] : io.y[g];
+    p.z[u] = VIEW ? io.vz[g] : io.z[g];
     p.c[u] = 0u;
     if (RGB && with_rgb) {
       const gptr<const uint8_t> q = io.rgb + 3 * (size_t)g;
@@ -641,15 +647,45 @@ __device__ __forceinline__ void bbox_zero(BboxAcc& a) {
 // One batch: the 16 B record of every point, the valid points' box and count,
 // row -1 for invalid points.  `g0` is the batch's first point, `rem` the points
 // of the tile from there on.
-template <class C, int HB>
+// A point of a frame with a filter, as every later phase sees it: rotated and
+// translated when asked for, p'_a = RN32(RN32(RN32(RN32(r[a][0] x) + RN32(r[a][1] y))
+// + RN32(r[a][2] z)) + t[a]); NaN when the point or p' is not finite or p'_z is
+// outside the height limit (an invalid point from then on).
+__device__ __forceinline__ void apply_xf(const FrameXf& f, float& x, float& y, float& z) {
+  const float X = x, Y = y, Z = z;
+  if (f.on & kXfRotate) {
+    x = __fadd_rn(__fadd_rn(__fadd_rn(__fmul_rn(f.r[0], X), __fmul_rn(f.r[1], Y)),
+                            __fmul_rn(f.r[2], Z)), f.t[0]);
+    y = __fadd_rn(__fadd_rn(__fadd_rn(__fmul_rn(f.r[3], X), __fmul_rn(f.r[4], Y)),
+                            __fmul_rn(f.r[5], Z)), f.t[1]);
+    z = __fadd_rn(__fadd_rn(__fadd_rn(__fmul_rn(f.r[6], X), __fmul_rn(f.r[7], Y)),
+                            __fmul_rn(f.r[8], Z)), f.t[2]);
+  }
+  const bool keep = finite3(X, Y, Z) && finite3(x, y, z) && z >= f.zlo && z <= f.zhi;
+  if (!keep) {
+    x = __builtin_nanf("");
+    y = x;
+    z = x;
+  }
+}
+
+// XF: the call has filters; the frame's (f) is applied first and the point
+// view written.
+template <class C, int HB, bool XF = false>
 __device__ __forceinline__ void bbox_batch(const Ws& ws, const GIo& io, BboxAcc& a,
-                                           const Pts<HB>& p, int64_t g0, int64_t rem,
-                                           uint32_t want) {
+                                           Pts<HB>& p, int64_t g0, int64_t rem, uint32_t want,
+                                           const FrameXf* xf = nullptr) {
 #pragma unroll
   for (int u = 0; u < HB; ++u) {
     const int64_t i = u * C::BLOCK + (int)threadIdx.x;
     if (i < rem) {
       const int64_t g = g0 + i;
+      if constexpr (XF) {
+        if (xf->on) apply_xf(*xf, p.x[u], p.y[u], p.z[u]);
+        ws.tx[g] = p.x[u];
+        ws.ty[g] = p.y[u];
+        ws.tz[g] = p.z[u];
+      }
       ws.rec[g] = make_float4(p.x[u], p.y[u], p.z[u], __uint_as_float(p.c[u]));
       if (finite3(p.x[u], p.y[u], p.z[u])) {
         const uint32_t ex = f2ord(p.x[u]), ey = f2ord(p.y[u]), ez = f2ord(p.z[u]);
@@ -713,10 +749,14 @@ __device__ void bbox_tile(const Ws& ws, const GIo& io, typename C::BboxSmem& bs,
   const int64_t cnt = min((int64_t)C::TB, fd.n - t0);
   BboxAcc a;
   bbox_zero(a);
+  const bool xf = (ws.hdr->filt & kFiltView) != 0;
+  FrameXf fx;
+  if (xf) fx = ws.xf[b];
   for (int64_t c = 0; c < cnt; c += C::BLOCK * HB) {
     Pts<HB> p;
     load_pts<C, HB>(io, p, fd.off + t0 + c, fd.off + fd.n - 1, io.rgb != nullptr);
-    bbox_batch<C, HB>(ws, io, a, p, fd.off + t0 + c, cnt - c, want);
+    if (xf) bbox_batch<C, HB, true>(ws, io, a, p, fd.off + t0 + c, cnt - c, want, &fx);
+    else bbox_batch<C, HB>(ws, io, a, p, fd.off + t0 + c, cnt - c, want);
   }
   bbox_finish<C>(ws, bs, a, b, persistent);
 }
@@ -857,7 +897,7 @@ __device__ void hist_tile(const Ws& ws, const GIo& io, typename C::HistSmem& hs,
   __syncthreads();
   for (int64_t c = 0; c < cnt; c += C::BLOCK * HB) {
     Pts<HB> p;
-    load_pts<C, HB>(io, p, fd.off + t0 + c, fd.off + fd.n - 1, false);
+    load_pts<C, HB, false, true>(io, p, fd.off + t0 + c, fd.off + fd.n - 1, false);
     hist_batch<C, HB>(ws, io, hs, f, key_mode, p, fd.off + t0 + c, cnt - c, want);
   }
   hist_finish<C>(ws, hs, b, f, persistent);
@@ -871,9 +911,10 @@ __device__ void hist_tile(const Ws& ws, const GIo& io, typename C::HistSmem& hs,
 // every iteration (of point 0 when there is no next batch), so the number of
 // loads in flight is the same on every path and the wait for the current
 // batch does not drain the next one.
-template <class C, int KIND, bool RGB>
+template <class C, int KIND, bool RGB, bool XF = false>
 __device__ void stream_big_tiles(const Ws& ws, const GIo& io, const CallHdr& hdr, BlockCtl& bc,
                                  typename SmemOf<C, KIND>::type& sm) {
+  constexpr bool VIEW = KIND == kHist;  // the histogram reads the point view
   constexpr int HB = kStreamBatch<KIND>;
   constexpr int64_t BS = (int64_t)C::BLOCK * HB;
   static_assert(C::TB % (C::BLOCK * HB) == 0, "big tile = whole load batches");
@@ -899,10 +940,12 @@ __device__ void stream_big_tiles(const Ws& ws, const GIo& io, const CallHdr& hdr
   int64_t cnt = min((int64_t)C::TB, fn - t0);
   int64_t c = 0;  // batch start within the tile
   Pts<HB> cur, nxt;
-  if (cnt > 0) load_pts<C, HB, RGB>(io, cur, off + t0, off + fn - 1, true);
-  else load_pts<C, HB, RGB>(io, cur, 0, 0, true);
+  if (cnt > 0) load_pts<C, HB, RGB, VIEW>(io, cur, off + t0, off + fn - 1, true);
+  else load_pts<C, HB, RGB, VIEW>(io, cur, 0, 0, true);
   BboxAcc acc;
   bbox_zero(acc);
+  FrameXf fx;
+  if constexpr (XF) fx = wave_uniform(ws.xf[b]);
   FrameParams f;
   if constexpr (KIND == kHist) {
     f = wave_uniform(bc.fpa[b]);
@@ -925,15 +968,19 @@ __device__ void stream_big_tiles(const Ws& ws, const GIo& io, const CallHdr& hdr
       }
     }
     const bool more = t2 < NT && cnt2 > 0;
-    load_pts<C, HB, RGB>(io, nxt, more ? off2 + t02 + c2 : 0, more ? off2 + fn2 - 1 : 0, true);
+    load_pts<C, HB, RGB, VIEW>(io, nxt, more ? off2 + t02 + c2 : 0, more ? off2 + fn2 - 1 : 0, true);
     if (cnt > 0) {
-      if constexpr (KIND == kBbox) bbox_batch<C, HB>(ws, io, acc, cur, off + t0 + c, cnt - c, hdr.want);
+      if constexpr (KIND == kBbox)
+        bbox_batch<C, HB, XF>(ws, io, acc, cur, off + t0 + c, cnt - c, hdr.want, &fx);
       else hist_batch<C, HB>(ws, io, sm.hist, f, hdr.key_mode, cur, off + t0 + c, cnt - c, hdr.want);
     }
     if (t2 != t) {
       if constexpr (KIND == kBbox) {
         bbox_finish<C>(ws, sm.bbox, acc, b, false);
         bbox_zero(acc);
+        if constexpr (XF) {
+          if (t2 < NT) fx = wave_uniform(ws.xf[b2]);
+        }
       } else {
         hist_finish<C>(ws, sm.hist, b, f, false);
         if (t2 < NT) {
@@ -1004,9 +1051,9 @@ __device__ void sort_tile(const Ws& ws, const GIo& io, typename C::SortSmem& S, 
 #pragma unroll
     for (int it = 0; it < C::SI; ++it) {
       const int64_t g = min(fd.off + wbase + it * 64, last);
-      xs[it] = io.x[g];
-      ys[it] = io.y[g];
-      zs[it] = io.z[g];
+      xs[it] = io.vx[g];
+      ys[it] = io.vy[g];
+      zs[it] = io.vz[g];
     }
 #pragma unroll
     for (int it = 0; it < C::SI; ++it) {
@@ -1252,7 +1299,7 @@ __device__ __forceinline__ void finalize_row(const GIo& io, uint32_t want, int64
     io.cz[row] = __fadd_rn(c.r[2], mean[2]);
   }
   if (want & kOutLocal) {
-    const float px = io.x[c.ref], py = io.y[c.ref], pz = io.z[c.ref];
+    const float px = io.vx[c.ref], py = io.vy[c.ref], pz = io.vz[c.ref];
     io.lx[row] = __fadd_rn(__fsub_rn(c.r[0], px), mean[0]);
     io.ly[row] = __fadd_rn(__fsub_rn(c.r[1], py), mean[1]);
     io.lz[row] = __fadd_rn(__fsub_rn(c.r[2], pz), mean[2]);
@@ -1972,8 +2019,14 @@ __global__ __launch_bounds__(C::BLOCK, (kMinWaves<C, KIND>)) void vg_pipeline_ke
   if (bc.item >= total && total > 0) return;
   if constexpr (KIND == kBbox || KIND == kHist) {
     if (cache_fd && hdr.N > 0) {
-      if (KIND == kBbox && io.rgb != nullptr) stream_big_tiles<C, KIND, true>(ws, io, hdr, bc, sm);
-      else stream_big_tiles<C, KIND, false>(ws, io, hdr, bc, sm);
+      if (KIND == kBbox && (hdr.filt & kFiltView)) {
+        if (io.rgb != nullptr) stream_big_tiles<C, KIND, true, true>(ws, io, hdr, bc, sm);
+        else stream_big_tiles<C, KIND, false, true>(ws, io, hdr, bc, sm);
+      } else if (KIND == kBbox && io.rgb != nullptr) {
+        stream_big_tiles<C, KIND, true>(ws, io, hdr, bc, sm);
+      } else {
+        stream_big_tiles<C, KIND, false>(ws, io, hdr, bc, sm);
+      }
       return;
     }
   }

@@ -61,6 +61,30 @@ class vg_nbd_out(ctypes.Structure):
                 ("marked", P), ("marked_cap", ctypes.c_int64)]
 
 
+class vg_filter(ctypes.Structure):
+    _fields_ = [("rot", ctypes.c_float * 9), ("trans", ctypes.c_float * 3), ("z_min", ctypes.c_float),
+                ("z_max", ctypes.c_float), ("min_points", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
+FILTER_TRANSFORM = 1
+
+
+def make_filter(rot=None, trans=None, z_min=-np.inf, z_max=np.inf, min_points=1):
+    """vg_filter for one cloud: rot (3x3) and trans (3) together or neither."""
+    f = vg_filter()
+    if rot is not None or trans is not None:
+        R = np.asarray(rot, dtype=np.float32).reshape(9)
+        T = np.asarray(trans, dtype=np.float32).reshape(3)
+        for k in range(9):
+            f.rot[k] = float(R[k])
+        for k in range(3):
+            f.trans[k] = float(T[k])
+        f.flags = FILTER_TRANSFORM
+    f.z_min, f.z_max = float(z_min), float(z_max)
+    f.min_points = int(min_points)
+    return f
+
+
 class VGError(RuntimeError):
     def __init__(self, status, where=""):
         self.status = status
@@ -74,11 +98,12 @@ EXPORTS = ["vg_status_string", "vg_default_tuning", "vg_tuning_supported", "vg_w
            "vg_downsample", "vg_downsample_ex", "vg_downsample_backward", "vg_batch_plan_create",
            "vg_batch_plan_set_graph", "vg_downsample_batched", "vg_batch_plan_set_timing",
            "vg_batch_plan_kernel_times", "vg_batch_plan_set_fail_waits", "vg_batch_plan_destroy",
-           "vg_downsample_noalloc", "vg_nbd_workspace_bytes", "vg_nbd_decimate"]
+           "vg_downsample_noalloc", "vg_nbd_workspace_bytes", "vg_nbd_decimate",
+           "vg_downsample_filtered", "vg_downsample_batched_filtered"]
 
 # Largest cloud of vg_downsample_noalloc and the size of its fixed device array.
 NOALLOC_MAX_POINTS = 1048576
-NOALLOC_SCRATCH_BYTES = 48 << 20
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 # vg_kernel_kind
 KERNEL_KINDS = ("init", "bbox", "hist", "sort", "reduce", "fixup", "pipeline")
@@ -114,6 +139,13 @@ def lib():
         L.vg_downsample_noalloc.argtypes = [ctypes.POINTER(vg_points), ctypes.c_int64,
                                             ctypes.c_float, ctypes.c_int, ctypes.POINTER(vg_cells),
                                             P, P, P]
+        L.vg_downsample_filtered.argtypes = [ctypes.POINTER(vg_points), ctypes.c_int64,
+                                             ctypes.c_float, ctypes.POINTER(vg_filter),
+                                             ctypes.POINTER(vg_cells), ctypes.POINTER(ctypes.c_int64),
+                                             ctypes.POINTER(vg_options)]
+        L.vg_downsample_batched_filtered.argtypes = [P, ctypes.POINTER(vg_points), P, P,
+                                                     ctypes.POINTER(vg_filter), ctypes.c_int,
+                                                     ctypes.POINTER(vg_cells), P, P, P]
         L.vg_nbd_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int32]
         L.vg_nbd_workspace_bytes.restype = ctypes.c_size_t
         L.vg_nbd_decimate.argtypes = [ctypes.POINTER(vg_points), ctypes.c_int64,
@@ -194,7 +226,7 @@ def _alloc_cells(cap, n_points, dev, outputs, have_rgb):
 
 
 def voxel_downsample(x, y, z, rgb=None, leaf=0.05, key_mode=KEY_LINEAR, tuning=None,
-                     outputs=ALL_OUTPUTS, workspace=None):
+                     outputs=ALL_OUTPUTS, workspace=None, filter=None):
     """Voxel-grid centroid filter of one cloud on the GPU (libvg: vg_downsample_ex).
 
     x, y, z: float32 CUDA tensors [n]; rgb: uint8 CUDA tensor [n, 3] or None.
@@ -213,10 +245,15 @@ def voxel_downsample(x, y, z, rgb=None, leaf=0.05, key_mode=KEY_LINEAR, tuning=N
                       ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), int(key_mode),
                       ctypes.pointer(tuning) if tuning is not None else None)
     m = ctypes.c_int64(0)
-    st = lib().vg_downsample_ex(ctypes.byref(pts), n, ctypes.c_float(leaf), ctypes.byref(cells),
-                                ctypes.byref(m), ctypes.byref(opts))
+    if filter is None:
+        st = lib().vg_downsample_ex(ctypes.byref(pts), n, ctypes.c_float(leaf), ctypes.byref(cells),
+                                    ctypes.byref(m), ctypes.byref(opts))
+    else:
+        st = lib().vg_downsample_filtered(ctypes.byref(pts), n, ctypes.c_float(leaf),
+                                          ctypes.byref(filter), ctypes.byref(cells), ctypes.byref(m),
+                                          ctypes.byref(opts))
     if st != VG_OK:
-        raise VGError(st, "vg_downsample_ex")
+        raise VGError(st, "vg_downsample_ex" if filter is None else "vg_downsample_filtered")
     mm = int(m.value)
     res = {k: (v if k == "point_cell" else v[:mm]) for k, v in o.items()}
     res["m"] = mm
@@ -388,8 +425,9 @@ class BatchPlan:
         o["frame_status"] = torch.empty(B, dtype=torch.int32, device=dev)
         return o, cells
 
-    def run(self, x, y, z, rgb, frame_offsets, leaves, outputs=ALL_OUTPUTS, out=None):
-        """Asynchronous launch; returns untrimmed output tensors (see out_offsets)."""
+    def run(self, x, y, z, rgb, frame_offsets, leaves, outputs=ALL_OUTPUTS, out=None, filters=None):
+        """Asynchronous launch; returns untrimmed output tensors (see out_offsets).
+        filters: None or a list of vg_filter, one per frame."""
         n = _check_points(x, y, z, rgb)
         offs = np.ascontiguousarray(frame_offsets, dtype=np.int64)
         lv = np.ascontiguousarray(leaves, dtype=np.float32)
@@ -400,12 +438,23 @@ class BatchPlan:
             out = self.alloc_outputs(n, B, x.device, outputs, rgb is not None)
         o, cells = out
         pts = vg_points(_ptr(x), _ptr(y), _ptr(z), _ptr(rgb))
-        st = lib().vg_downsample_batched(
-            self._h, ctypes.byref(pts), ctypes.c_void_p(offs.ctypes.data),
-            ctypes.c_void_p(lv.ctypes.data), B, ctypes.byref(cells), _ptr(o["out_offsets"]),
-            _ptr(o["frame_status"]), ctypes.c_void_p(torch.cuda.current_stream(x.device).cuda_stream))
+        stream = ctypes.c_void_p(torch.cuda.current_stream(x.device).cuda_stream)
+        if filters is None:
+            st = lib().vg_downsample_batched(
+                self._h, ctypes.byref(pts), ctypes.c_void_p(offs.ctypes.data),
+                ctypes.c_void_p(lv.ctypes.data), B, ctypes.byref(cells), _ptr(o["out_offsets"]),
+                _ptr(o["frame_status"]), stream)
+        else:
+            if len(filters) != B:
+                raise ValueError("one filter per frame")
+            farr = (vg_filter * B)(*filters)
+            st = lib().vg_downsample_batched_filtered(
+                self._h, ctypes.byref(pts), ctypes.c_void_p(offs.ctypes.data),
+                ctypes.c_void_p(lv.ctypes.data), farr, B, ctypes.byref(cells),
+                _ptr(o["out_offsets"]), _ptr(o["frame_status"]), stream)
         if st != VG_OK:
-            raise VGError(st, "vg_downsample_batched")
+            raise VGError(st, "vg_downsample_batched" if filters is None else
+                          "vg_downsample_batched_filtered")
         return o
 
     def close(self):

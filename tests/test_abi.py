@@ -6,6 +6,7 @@ CPU; calls that would need a device report VG_ERR_DEVICE instead of crashing.
 import ctypes
 import re
 
+import numpy as np
 import pytest
 
 from paper_2102_11084_amd import vg
@@ -126,3 +127,26 @@ def test_batch_plan_checks():
     assert L.vg_batch_plan_set_fail_waits(None, 1) == vg.VG_ERR_ARG
     cnt = ctypes.c_int(5)
     assert L.vg_batch_plan_kernel_times(None, None, None, 0, ctypes.byref(cnt)) == vg.VG_ERR_ARG
+
+
+def test_filter_arguments_rejected_before_any_launch():
+    import ctypes
+    L = vg.lib()
+    dummy = ctypes.c_void_p(16)
+    pts = vg.vg_points(dummy, dummy, dummy, None)
+    cells = vg.vg_cells()
+    m = ctypes.c_int64(7)
+    opts = vg.vg_options()
+    for f in (vg.make_filter(z_min=1.0, z_max=0.0), vg.make_filter(z_min=float("nan")),
+              vg.make_filter(rot=np.full((3, 3), np.inf), trans=np.zeros(3))):
+        st = L.vg_downsample_filtered(ctypes.byref(pts), 10, ctypes.c_float(0.1), ctypes.byref(f),
+                                      ctypes.byref(cells), ctypes.byref(m), ctypes.byref(opts))
+        assert st == vg.VG_ERR_ARG and m.value == 0
+    bad = vg.make_filter()
+    bad.flags = 8
+    assert L.vg_downsample_filtered(ctypes.byref(pts), 10, ctypes.c_float(0.1), ctypes.byref(bad),
+                                    ctypes.byref(cells), ctypes.byref(m),
+                                    ctypes.byref(opts)) == vg.VG_ERR_ARG
+    assert L.vg_downsample_filtered(ctypes.byref(pts), 10, ctypes.c_float(0.1), None,
+                                    ctypes.byref(cells), ctypes.byref(m),
+                                    ctypes.byref(opts)) == vg.VG_ERR_ARG
