@@ -307,6 +307,82 @@ def nbd_leg(tuning, dev, reps=5, oracle_runs=1):
     return leg
 
 
+def ingest_leg(x, y, z, rgb, offs, leaves, d, plan, outs, o_ref, tuning, dev, steps, use_graph):
+    """The batch with its points in pinned host memory instead of HBM: (a) an
+    explicit copy to the device then the call, (b) the call reading the mapped
+    host memory itself, once, in its bbox pass (the paper's zero-copy)."""
+    import torch
+
+    from paper_2102_11084_amd import vg
+    stream = torch.cuda.current_stream(dev)
+    N = int(offs[-1])
+    B = len(leaves)
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    # (a) pinned torch tensors copied in, then the same call as the headline
+    pinned = [torch.from_numpy(np.ascontiguousarray(a)).pin_memory() for a in (x, y, z, rgb.reshape(-1))]
+    for _ in range(2):
+        for t, p in zip(d, pinned):
+            t.copy_(p, non_blocking=True)
+        plan.run(*d, offs, leaves, out=outs)
+    torch.cuda.synchronize()
+    e0, e1, e2 = ev(), ev(), ev()
+    e0.record(stream)
+    for _ in range(steps):
+        for t, p in zip(d, pinned):
+            t.copy_(p, non_blocking=True)
+    e1.record(stream)
+    for _ in range(steps):
+        for t, p in zip(d, pinned):
+            t.copy_(p, non_blocking=True)
+        plan.run(*d, offs, leaves, out=outs)
+    e2.record(stream)
+    torch.cuda.synchronize()
+    copy_ms = e0.elapsed_time(e1) / steps
+    copy_call_ms = e1.elapsed_time(e2) / steps
+    del pinned
+    # (b) mapped host memory read by the bbox pass
+    buf = vg.HostBuffer(15 * N)
+    ptrs, off = [], 0
+    for a in (x, y, z):
+        buf.view(np.float32, N, off)[:] = a
+        ptrs.append(buf.device + off)
+        off += 4 * N
+    buf.view(np.uint8, 3 * N, off)[:] = rgb.reshape(-1)
+    ptrs.append(buf.device + off)
+    hplan = vg.BatchPlan(B, N, vg.KEY_LINEAR, tuning, use_graph=use_graph)
+    hplan.set_host_input(True)
+    hout = hplan.alloc_outputs(N, B, dev, outputs=("xyz", "rgb", "count", "key"))
+    for _ in range(2):
+        hplan.run_host(*ptrs, N, offs, leaves, hout, stream)
+    torch.cuda.synchronize()
+    f0, f1 = ev(), ev()
+    f0.record(stream)
+    for _ in range(steps):
+        hplan.run_host(*ptrs, N, offs, leaves, hout, stream)
+    f1.record(stream)
+    torch.cuda.synchronize()
+    zc_ms = f0.elapsed_time(f1) / steps
+    h = {k: v.cpu().numpy() for k, v in hout[0].items()}
+    m = int(o_ref["out_offsets"][-1])
+    same = bool(np.array_equal(h["out_offsets"], o_ref["out_offsets"]) and
+                all(np.array_equal(h[k][:m].view(np.uint8), o_ref[k][:m].view(np.uint8))
+                    for k in ("x", "y", "z", "rgb", "count", "key")))
+    hplan.close()
+    buf.close()
+    in_bytes = 15 * N
+    return {
+        "workload": f"the {B}-frame batch with its {N} points (x, y, z, rgb: {in_bytes} B) in pinned "
+                    "host memory",
+        "copy_only_ms": round(copy_ms, 3), "copy_gbs": round(in_bytes / (copy_ms * 1e-3) / 1e9, 1),
+        "copy_then_call_ms": round(copy_call_ms, 3),
+        "copy_then_call_mpoints_s": round(N / (copy_call_ms * 1e-3) / 1e6, 1),
+        "zero_copy_call_ms": round(zc_ms, 3),
+        "zero_copy_mpoints_s": round(N / (zc_ms * 1e-3) / 1e6, 1),
+        "zero_copy_input_gbs": round(in_bytes / (zc_ms * 1e-3) / 1e9, 1),
+        "zero_copy_bit_identical": same,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -542,6 +618,42 @@ def main():
                                  "backward_mpoints_s": round(3_200_000 / (bwd_ms * 1e-3) / 1e6, 1),
                                  "backward_gbs": round(32 * 3_200_000 / (bwd_ms * 1e-3) / 1e9, 1)},
         }
+        # the same frames through the filtered form: each frame moved into the
+        # global frame by its own camera pose, height-limited to 0.05..2.0 m,
+        # cells of fewer than 3 points dropped
+        filters = []
+        for b in range(len(leaves)):
+            R, t = dg.camera_pose(8000 + b)
+            filters.append(vg.make_filter(rot=R, trans=t, z_min=0.05, z_max=2.0, min_points=3))
+        fplan = vg.BatchPlan(len(leaves), N, vg.KEY_LINEAR, tuning, use_graph=not args.no_graph)
+        fouts = fplan.alloc_outputs(N, len(leaves), dev, outputs=out_set)
+        for _ in range(max(args.warmup, 2)):
+            fplan.run(*d, offs, leaves, out=fouts, filters=filters)
+        torch.cuda.synchronize()
+        f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        f0.record(stream)
+        for _ in range(args.steps):
+            fplan.run(*d, offs, leaves, out=fouts, filters=filters)
+        f1.record(stream)
+        torch.cuda.synchronize()
+        fms = f0.elapsed_time(f1) / args.steps
+        fo = {k: v.cpu().numpy() for k, v in fouts[0].items() if k in ("out_offsets", "frame_status", "count")}
+        fplan.close()
+        assert (fo["frame_status"] == 0).all(), "a filtered frame failed"
+        kept = int(fo["count"][:int(fo["out_offsets"][-1])].astype(np.int64).sum())
+        result["legs"]["filtered_batch"] = {
+            "workload": f"the {len(leaves)} frames, each moved by its own camera pose into the "
+                        "global frame, height limit 0.05..2.0 m, cells of fewer than 3 points dropped",
+            "ms_per_step": round(fms, 4), "mpoints_s": round(N / (fms * 1e-3) / 1e6, 1),
+            "over_unfiltered": round(fms / ev_ms, 3), "cells": int(fo["out_offsets"][-1]),
+            "points_in_kept_cells": kept}
+        log(f"leg: filtered batch: {fms:.3f} ms/step, {result['legs']['filtered_batch']['cells']} cells")
+        ing = ingest_leg(x, y, z, rgb, offs, leaves, d, plan, outs, o, tuning, dev,
+                         max(3, min(args.steps, 10)), not args.no_graph)
+        if not ing["zero_copy_bit_identical"]:
+            raise SystemExit("bench.py: the call on host-memory points differs from the device-resident one")
+        result["legs"]["host_ingest"] = ing
+        log(f"leg: host ingest: copy+call {ing['copy_then_call_ms']} ms, zero-copy {ing['zero_copy_call_ms']} ms")
         if not args.no_config_legs:
             cfg = []
             cfg.append(single_cloud_leg("640x480 RGB-D frame, plain path", dg.frame_640x480(), 0.05,

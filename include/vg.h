@@ -267,6 +267,23 @@ vg_status vg_batch_plan_set_timing(vg_batch_plan *plan, int enable);
 vg_status vg_batch_plan_kernel_times(vg_batch_plan *plan, int *kinds, float *ms, int cap,
                                      int *count);
 
+/* ---- input in host memory (the paper's zero-copy theme, Sec. I, II-B, III) ----
+ * On the paper's board the GPU reads the camera's buffer in shared memory
+ * instead of copying it.  Here the analogue for a discrete GPU: points in
+ * pinned host memory mapped into the device's address space, read by the
+ * kernels over the host link.
+ * vg_host_alloc: pinned, mapped host memory of `bytes` bytes; *host is the
+ * host address (for filling), *device the address to pass to the library.
+ * Free with vg_host_free(host).  VG_ERR_DEVICE if the runtime refuses.
+ * vg_batch_plan_set_host_input: while on != 0, later calls on the plan take
+ * their points from such memory: the bbox pass reads every point once from
+ * there (its validity, box and record pass) and writes a device copy of the
+ * coordinates that every later pass reads, so the host link carries the input
+ * exactly once.  Results are bit-identical to device-resident input. */
+vg_status vg_host_alloc(size_t bytes, void **host, void **device);
+vg_status vg_host_free(void *host);
+vg_status vg_batch_plan_set_host_input(vg_batch_plan *plan, int on);
+
 /* Test support for callers' error handling (not in the paper): while enable
  * != 0, each later call on the plan starts with the device-side time-out flag
  * raised, as a bounded wait that timed out would raise it.  Every kernel then

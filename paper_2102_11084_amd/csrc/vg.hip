@@ -264,7 +264,7 @@ bool fill_staging(char* st, const Layout& L, const Variant& v, const vg_points* 
                   const int64_t* offs, const float* leaves, const float* invs, int B,
                   const vg_cells* out, int64_t* out_offsets, int32_t* frame_status, int key_mode,
                   int fail_waits, CallHdr* hdr_out, const Ws& ws,
-                  const vg_filter* filters = nullptr) {
+                  const vg_filter* filters = nullptr, bool host_input = false) {
   CallHdr hdr;
   std::memset(&hdr, 0, sizeof hdr);
   hdr.B = B;
@@ -325,6 +325,15 @@ bool fill_staging(char* st, const Layout& L, const Variant& v, const vg_points* 
       hdr.want |= kOutCount;
       hdr.filt |= kFiltCountInternal;
     }
+  }
+  // points in host memory: the bbox pass reads them once and writes the view
+  // every later pass reads from device memory
+  if (host_input) {
+    if (!filters) std::memset(st + L.xf, 0, sizeof(FrameXf) * (size_t)B);
+    hdr.filt |= kFiltView;
+    io.vx = ws.tx;
+    io.vy = ws.ty;
+    io.vz = ws.tz;
   }
   FrameDesc* fd = reinterpret_cast<FrameDesc*>(st + L.fd);
   uint32_t* tpb = reinterpret_cast<uint32_t*>(st + L.tpb);
@@ -1018,6 +1027,7 @@ struct vg_batch_plan {
   LaunchTimer* timer;  // non-null while timing is on
   int fail_waits;      // test support: calls start with the time-out flag raised
   bool graph_sparse;   // the captured graph holds the sparse-cell pass
+  bool host_input;     // the points of later calls are in mapped host memory
 };
 
 extern "C" {
@@ -1050,6 +1060,7 @@ vg_status vg_batch_plan_create(int max_frames, int64_t max_total_points, vg_key_
   P->timer = nullptr;
   P->fail_waits = 0;
   P->graph_sparse = false;
+  P->host_input = false;
   vg_status rc = VG_OK;
   if (hipGetDevice(&P->device) != hipSuccess) rc = VG_ERR_DEVICE;
   if (rc == VG_OK && (P->cus = device_cus(P->device)) <= 0) rc = VG_ERR_DEVICE;
@@ -1076,6 +1087,35 @@ vg_status vg_batch_plan_set_graph(vg_batch_plan* plan, int use_graph) {
   if (!plan) return VG_ERR_ARG;
   plan->use_graph = use_graph ? 1 : 0;
   return VG_OK;
+}
+
+vg_status vg_batch_plan_set_host_input(vg_batch_plan* plan, int on) {
+  if (!plan) return VG_ERR_ARG;
+  plan->host_input = on != 0;
+  return VG_OK;
+}
+
+vg_status vg_host_alloc(size_t bytes, void** host, void** device) {
+  if (!host || !device) return VG_ERR_ARG;
+  *host = nullptr;
+  *device = nullptr;
+  void* h = nullptr;
+  if (hipHostMalloc(&h, bytes ? bytes : 1, hipHostMallocMapped | hipHostMallocPortable) !=
+      hipSuccess)
+    return VG_ERR_DEVICE;
+  void* d = nullptr;
+  if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess || !d) {
+    (void)hipHostFree(h);
+    return VG_ERR_DEVICE;
+  }
+  *host = h;
+  *device = d;
+  return VG_OK;
+}
+
+vg_status vg_host_free(void* host) {
+  if (!host) return VG_ERR_ARG;
+  return hipHostFree(host) == hipSuccess ? VG_OK : VG_ERR_DEVICE;
 }
 
 vg_status vg_batch_plan_set_fail_waits(vg_batch_plan* plan, int enable) {
@@ -1153,7 +1193,8 @@ vg_status downsample_batch(vg_batch_plan* P, const vg_points* p, const int64_t* 
   }
   CallHdr hdr;
   if (!fill_staging(P->staging, P->L, *P->v, p, offs, leaf, P->invs, B, out, out_offsets,
-                    frame_status, P->key_mode, P->fail_waits, &hdr, P->ws, filters))
+                    frame_status, P->key_mode, P->fail_waits, &hdr, P->ws, filters,
+                    P->host_input))
     return VG_ERR_ARG;
   const bool sparse = (hdr.filt & kFiltMinPts) != 0;
   vg_status rc = VG_OK;

@@ -222,3 +222,21 @@ def upstream_grad(m, seed):
     """Upstream gradient dL/dcentroid ~ N(0, 1), shape (m, 3), float32."""
     rng = np.random.default_rng(seed)
     return rng.standard_normal((m, 3)).astype(np.float32)
+
+
+def camera_pose(seed):
+    """A depth camera on a ground robot, as a rigid transform of camera points
+    into the global frame: optical axes (x right, y down, z forward) turned to
+    the robot's (x forward, y left, z up), pitched by up to +-0.2 rad, yawed
+    anywhere, mounted 0.3 m up at a random spot of a 10 x 10 m floor.  Returns
+    (R 3x3 float32, t 3 float32) with p_global = R p_camera + t."""
+    rng = np.random.default_rng(seed)
+    yaw, pitch = rng.uniform(-np.pi, np.pi), rng.uniform(-0.2, 0.2)
+    cam = np.array([[0, 0, 1], [-1, 0, 0], [0, -1, 0]], np.float64)
+    cp, sp = np.cos(pitch), np.sin(pitch)
+    Ry = np.array([[cp, 0, sp], [0, 1, 0], [-sp, 0, cp]])
+    cy, sy = np.cos(yaw), np.sin(yaw)
+    Rz = np.array([[cy, -sy, 0], [sy, cy, 0], [0, 0, 1]])
+    R = (Rz @ Ry @ cam).astype(np.float32)
+    t = np.array([rng.uniform(-5, 5), rng.uniform(-5, 5), 0.3], np.float32)
+    return R, t

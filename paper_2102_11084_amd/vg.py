@@ -99,7 +99,8 @@ EXPORTS = ["vg_status_string", "vg_default_tuning", "vg_tuning_supported", "vg_w
            "vg_batch_plan_set_graph", "vg_downsample_batched", "vg_batch_plan_set_timing",
            "vg_batch_plan_kernel_times", "vg_batch_plan_set_fail_waits", "vg_batch_plan_destroy",
            "vg_downsample_noalloc", "vg_nbd_workspace_bytes", "vg_nbd_decimate",
-           "vg_downsample_filtered", "vg_downsample_batched_filtered"]
+           "vg_downsample_filtered", "vg_downsample_batched_filtered", "vg_host_alloc",
+           "vg_host_free", "vg_batch_plan_set_host_input"]
 
 # Largest cloud of vg_downsample_noalloc and the size of its fixed device array.
 NOALLOC_MAX_POINTS = 1048576
@@ -146,6 +147,9 @@ def lib():
         L.vg_downsample_batched_filtered.argtypes = [P, ctypes.POINTER(vg_points), P, P,
                                                      ctypes.POINTER(vg_filter), ctypes.c_int,
                                                      ctypes.POINTER(vg_cells), P, P, P]
+        L.vg_host_alloc.argtypes = [ctypes.c_size_t, ctypes.POINTER(P), ctypes.POINTER(P)]
+        L.vg_host_free.argtypes = [P]
+        L.vg_batch_plan_set_host_input.argtypes = [P, ctypes.c_int]
         L.vg_nbd_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int32]
         L.vg_nbd_workspace_bytes.restype = ctypes.c_size_t
         L.vg_nbd_decimate.argtypes = [ctypes.POINTER(vg_points), ctypes.c_int64,
@@ -373,6 +377,35 @@ def voxel_downsample_autograd(x, y, z, leaf, key_mode=KEY_LINEAR):
     return VoxelDownsampleFn.apply(x, y, z, leaf, key_mode)
 
 
+class HostBuffer:
+    """Pinned host memory mapped into the device (vg_host_alloc): `array` is a
+    numpy view for filling it on the host, `device` the address the library
+    reads it at."""
+
+    def __init__(self, nbytes):
+        h, d = ctypes.c_void_p(), ctypes.c_void_p()
+        st = lib().vg_host_alloc(int(nbytes), ctypes.byref(h), ctypes.byref(d))
+        if st != VG_OK:
+            raise VGError(st, "vg_host_alloc")
+        self._h, self.device, self.nbytes = h, int(d.value), int(nbytes)
+        self.array = np.ctypeslib.as_array((ctypes.c_uint8 * max(int(nbytes), 1)).from_address(h.value))
+
+    def view(self, dtype, count, offset=0):
+        return self.array[offset:offset + count * np.dtype(dtype).itemsize].view(dtype)
+
+    def close(self):
+        if self._h:
+            self.array = None
+            lib().vg_host_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class BatchPlan:
     """Many frames of uneven size and leaf in one launch (vg_downsample_batched)."""
 
@@ -405,6 +438,31 @@ class BatchPlan:
         st = lib().vg_batch_plan_set_fail_waits(self._h, 1 if enable else 0)
         if st != VG_OK:
             raise VGError(st, "vg_batch_plan_set_fail_waits")
+
+    def set_host_input(self, on: bool):
+        """Later runs read their points from mapped host memory (run_host)."""
+        st = lib().vg_batch_plan_set_host_input(self._h, 1 if on else 0)
+        if st != VG_OK:
+            raise VGError(st, "vg_batch_plan_set_host_input")
+
+    def run_host(self, xp, yp, zp, rgbp, n, frame_offsets, leaves, out, stream):
+        """run() with the points at device addresses of host memory (HostBuffer.device
+        plus an offset); `out` from alloc_outputs; `stream` a torch stream."""
+        offs = np.ascontiguousarray(frame_offsets, dtype=np.int64)
+        lv = np.ascontiguousarray(leaves, dtype=np.float32)
+        B = lv.size
+        if offs.size != B + 1 or offs[-1] != n:
+            raise ValueError("frame_offsets must have B+1 entries ending at n")
+        o, cells = out
+        pts = vg_points(ctypes.c_void_p(xp), ctypes.c_void_p(yp), ctypes.c_void_p(zp),
+                        ctypes.c_void_p(rgbp) if rgbp else None)
+        st = lib().vg_downsample_batched(
+            self._h, ctypes.byref(pts), ctypes.c_void_p(offs.ctypes.data),
+            ctypes.c_void_p(lv.ctypes.data), B, ctypes.byref(cells), _ptr(o["out_offsets"]),
+            _ptr(o["frame_status"]), ctypes.c_void_p(stream.cuda_stream))
+        if st != VG_OK:
+            raise VGError(st, "vg_downsample_batched")
+        return o
 
     def kernel_times(self):
         """[(kind name, ms)] of the last run's kernel launches, in launch order (waits)."""

@@ -20,17 +20,7 @@ def rotation(rng):
 
 
 def camera_pose(rng):
-    """A camera on a robot: yaw about the global z, pitch of a few degrees,
-    camera z (depth) along the global x, mounted about 0.3 m up."""
-    yaw, pitch = rng.uniform(-np.pi, np.pi), rng.uniform(-0.2, 0.2)
-    cam = np.array([[0, 0, 1], [-1, 0, 0], [0, -1, 0]], np.float64)   # optical -> base axes
-    cp, sp = np.cos(pitch), np.sin(pitch)
-    Ry = np.array([[cp, 0, sp], [0, 1, 0], [-sp, 0, cp]])
-    cy, sy = np.cos(yaw), np.sin(yaw)
-    Rz = np.array([[cy, -sy, 0], [sy, cy, 0], [0, 0, 1]])
-    R = (Rz @ Ry @ cam).astype(np.float32)
-    t = np.array([rng.uniform(-5, 5), rng.uniform(-5, 5), 0.3], np.float32)
-    return R, t
+    return dg.camera_pose(int(rng.integers(0, 2 ** 31)))
 
 
 def plain(x, y, z, rgb, leaf, kw):
