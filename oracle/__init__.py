@@ -70,6 +70,18 @@ def _bind(lib):
     lib.vgo_downsample_filtered.argtypes = [P, P, P, P, i64, f32, c_int, P, P, f32, f32,
                                             ctypes.c_uint32] + [P] * 12
     lib.vgo_downsample_filtered.restype = c_int
+    lib.vgo_map_create.argtypes = [f32]
+    lib.vgo_map_create.restype = P
+    lib.vgo_map_destroy.argtypes = [P]
+    lib.vgo_map_destroy.restype = None
+    lib.vgo_map_mark.argtypes = [P, P, P, P, i64, ctypes.c_uint32]
+    lib.vgo_map_mark.restype = i64
+    lib.vgo_map_clear.argtypes = [P, P, P, f32, f32, f32, f32, ctypes.c_int32, ctypes.c_int32, f32, f32]
+    lib.vgo_map_clear.restype = i64
+    lib.vgo_map_expire.argtypes = [P, ctypes.c_uint32]
+    lib.vgo_map_expire.restype = i64
+    lib.vgo_map_export.argtypes = [P, P, P, i64]
+    lib.vgo_map_export.restype = i64
     return lib
 
 
@@ -258,3 +270,46 @@ def nbd_decimate(x, y, z, leaf, radius, umbral, seed, round_size=1000, lib=None)
     r = int(rounds[0])
     return dict(keep=keep[:n].astype(bool), count0=count0[:n], marked=marked[:min(r, cap)],
                 rounds=r)
+
+
+class VoxelMap:
+    """The global voxel map (mark / clear in a camera frustum / expire; see
+    vgo.cpp for the readings)."""
+
+    def __init__(self, res, lib=None):
+        self.lib = lib or load()
+        self.h = self.lib.vgo_map_create(np.float32(res))
+        if not self.h:
+            raise OracleError(ERR_ARG)
+
+    def mark(self, x, y, z, stamp):
+        x, y, z = _f32(x), _f32(y), _f32(z)
+        return int(self.lib.vgo_map_mark(self.h, _ptr(x), _ptr(y), _ptr(z), x.size, int(stamp)))
+
+    def clear(self, rot, trans, fx, fy, cx, cy, width, height, z_near, z_far):
+        R = np.ascontiguousarray(rot, dtype=np.float32).reshape(9)
+        T = np.ascontiguousarray(trans, dtype=np.float32).reshape(3)
+        return int(self.lib.vgo_map_clear(self.h, _ptr(R), _ptr(T), np.float32(fx), np.float32(fy),
+                                          np.float32(cx), np.float32(cy), int(width), int(height),
+                                          np.float32(z_near), np.float32(z_far)))
+
+    def expire(self, min_stamp):
+        return int(self.lib.vgo_map_expire(self.h, int(min_stamp)))
+
+    def export(self):
+        n = int(self.lib.vgo_map_export(self.h, None, None, 0))
+        keys = np.zeros(max(n, 1), np.uint64)
+        stamps = np.zeros(max(n, 1), np.uint32)
+        self.lib.vgo_map_export(self.h, _ptr(keys), _ptr(stamps), n)
+        return keys[:n], stamps[:n]
+
+    def close(self):
+        if self.h:
+            self.lib.vgo_map_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

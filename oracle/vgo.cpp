@@ -395,6 +395,151 @@ int vgo_downsample_filtered(const float* x, const float* y, const float* z, cons
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
+// Global voxel map (Sec. II-C: the costmap layer marks the cells of each new
+// cloud as occupied and clears, as free, the cells inside the sensor's view,
+// on a sparse map of the whole space; the paper times these operations and
+// names a GPU map as future work).  As read here:
+//   * voxels of edge `res` on a grid fixed in the global frame:
+//     k_a = floor(RN32(p_a * inv_res)), inv_res = RN32(1/res), for
+//     -2^20 <= k_a < 2^20 (points outside, or not finite, are skipped);
+//     key = (k_x + 2^20) | (k_y + 2^20) << 21 | (k_z + 2^20) << 42;
+//   * mark: every voxel holding a point of the cloud gets the time stamp
+//     (inserted, or re-stamped);
+//   * clear: every voxel whose centre c_a = RN32(RN32(k_a + 0.5) * res) lies in
+//     the camera frustum is removed.  With the camera pose (R, t) (camera to
+//     global) and d_a = RN32(c_a - t_a), the centre in the camera frame is
+//     q_j = RN32(RN32(RN32(R[0][j] d_0) + RN32(R[1][j] d_1)) + RN32(R[2][j] d_2));
+//     it is inside iff z_near <= q_2 <= z_far and the pixel coordinates
+//     u = RN32(RN32(fx * RN32(q_0 / q_2)) + cx), v = RN32(RN32(fy * RN32(q_1 / q_2)) + cy)
+//     satisfy -0.5 <= u <= width - 0.5 and -0.5 <= v <= height - 0.5;
+//   * expire: voxels stamped before a given stamp are removed (the layer's
+//     temporal decay).
+// The oracle keeps a std::map from key to stamp.
+
+namespace {
+
+struct VoxelMap {
+  float res, inv;
+  std::map<uint64_t, uint32_t> vox;
+};
+
+const int32_t kVoxelHalfRange = 1 << 20;
+
+bool voxel_key(const VoxelMap& m, float x, float y, float z, uint64_t* key) {
+  if (!point_is_valid(x, y, z)) return false;
+  const float p[3] = {x, y, z};
+  uint64_t k = 0;
+  for (int a = 0; a < 3; ++a) {
+    float t = p[a] * m.inv;
+    float f = std::floor(t);
+    if (!(f >= -(float)kVoxelHalfRange && f < (float)kVoxelHalfRange)) return false;
+    int64_t c = (int64_t)f + kVoxelHalfRange;
+    k |= (uint64_t)c << (21 * a);
+  }
+  *key = k;
+  return true;
+}
+
+bool in_frustum(const VoxelMap& m, uint64_t key, const float* R, const float* t, float fx,
+                float fy, float cx, float cy, int32_t width, int32_t height, float z_near,
+                float z_far) {
+  float d[3];
+  for (int a = 0; a < 3; ++a) {
+    int64_t k = (int64_t)((key >> (21 * a)) & ((1u << 21) - 1u)) - kVoxelHalfRange;
+    float kc = (float)k + 0.5f;
+    float c = kc * m.res;
+    d[a] = c - t[a];
+  }
+  float q[3];
+  for (int j = 0; j < 3; ++j) {
+    float s0 = R[0 * 3 + j] * d[0];
+    float s1 = R[1 * 3 + j] * d[1];
+    float s2 = R[2 * 3 + j] * d[2];
+    float s01 = s0 + s1;
+    q[j] = s01 + s2;
+  }
+  if (!(q[2] >= z_near && q[2] <= z_far)) return false;
+  float rx = q[0] / q[2];
+  float ry = q[1] / q[2];
+  float u = fx * rx + cx;
+  float v = fy * ry + cy;
+  return u >= -0.5f && u <= (float)width - 0.5f && v >= -0.5f && v <= (float)height - 0.5f;
+}
+
+}  // namespace
+
+extern "C" {
+
+void* vgo_map_create(float res) {
+  if (!std::isfinite(res) || !(res > 0.0f)) return nullptr;
+  VoxelMap* m = new VoxelMap();
+  m->res = res;
+  m->inv = 1.0f / res;
+  return m;
+}
+
+void vgo_map_destroy(void* m) { delete static_cast<VoxelMap*>(m); }
+
+// Marks the voxels of n points with `stamp`; returns the points skipped.
+int64_t vgo_map_mark(void* mp, const float* x, const float* y, const float* z, int64_t n,
+                     uint32_t stamp) {
+  VoxelMap& m = *static_cast<VoxelMap*>(mp);
+  int64_t skipped = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    uint64_t k;
+    if (voxel_key(m, x[i], y[i], z[i], &k)) m.vox[k] = stamp;
+    else ++skipped;
+  }
+  return skipped;
+}
+
+// Clears the voxels in the frustum; returns how many.
+int64_t vgo_map_clear(void* mp, const float* R, const float* t, float fx, float fy, float cx,
+                      float cy, int32_t width, int32_t height, float z_near, float z_far) {
+  VoxelMap& m = *static_cast<VoxelMap*>(mp);
+  int64_t cleared = 0;
+  for (auto it = m.vox.begin(); it != m.vox.end();) {
+    if (in_frustum(m, it->first, R, t, fx, fy, cx, cy, width, height, z_near, z_far)) {
+      it = m.vox.erase(it);
+      ++cleared;
+    } else {
+      ++it;
+    }
+  }
+  return cleared;
+}
+
+int64_t vgo_map_expire(void* mp, uint32_t min_stamp) {
+  VoxelMap& m = *static_cast<VoxelMap*>(mp);
+  int64_t gone = 0;
+  for (auto it = m.vox.begin(); it != m.vox.end();) {
+    if (it->second < min_stamp) {
+      it = m.vox.erase(it);
+      ++gone;
+    } else {
+      ++it;
+    }
+  }
+  return gone;
+}
+
+// The voxels in ascending key order (at most cap); returns their number.
+int64_t vgo_map_export(void* mp, uint64_t* keys, uint32_t* stamps, int64_t cap) {
+  VoxelMap& m = *static_cast<VoxelMap*>(mp);
+  int64_t i = 0;
+  for (const auto& kv : m.vox) {
+    if (i < cap) {
+      keys[i] = kv.first;
+      stamps[i] = kv.second;
+    }
+    ++i;
+  }
+  return i;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
 // Neighbour-bucket decimation (arXiv 2102.11084, Sec. II-C, Alg. 1).
 //
 // What the paper's own GPU filter computes, as read here:

@@ -9,6 +9,7 @@ import os
 import pytest
 
 import filter_pins
+import map_pins
 import nbd_pins
 import oracle
 import oracle_pins as pins
@@ -62,6 +63,18 @@ MUTANTS = {
     "filter_min_points_strict": ("if (acount[k] < min_points) continue;", "if (acount[k] <= min_points) continue;"),
     "filter_rows_not_renumbered": ("point_cell[i] = apc[i] < 0 ? -1 : (int32_t)row[apc[i]];",
                                    "point_cell[i] = apc[i];"),
+    # global voxel map
+    "map_floor_to_trunc": ("float f = std::floor(t);", "float f = std::trunc(t);"),
+    "map_key_axis_slip": ("k |= (uint64_t)c << (21 * a);", "k |= (uint64_t)c << (21 * (2 - a));"),
+    "map_range_inclusive": ("if (!(f >= -(float)kVoxelHalfRange && f < (float)kVoxelHalfRange)) return false;",
+                            "if (!(f >= -(float)kVoxelHalfRange && f <= (float)kVoxelHalfRange)) return false;"),
+    "map_rotation_not_transposed": ("float s1 = R[1 * 3 + j] * d[1];", "float s1 = R[j * 3 + 1] * d[1];"),
+    "map_centre_at_corner": ("float kc = (float)k + 0.5f;", "float kc = (float)k;"),
+    "map_u_bound_off": ("u <= (float)width - 0.5f", "u <= (float)width + 0.5f"),
+    "map_far_exclusive": ("q[2] >= z_near && q[2] <= z_far", "q[2] >= z_near && q[2] < z_far"),
+    "map_keeps_first_stamp": ("if (voxel_key(m, x[i], y[i], z[i], &k)) m.vox[k] = stamp;",
+                              "if (voxel_key(m, x[i], y[i], z[i], &k)) m.vox.insert({k, stamp});"),
+    "map_expire_inclusive": ("if (it->second < min_stamp) {", "if (it->second <= min_stamp) {"),
 }
 
 
@@ -74,7 +87,8 @@ def test_mutant_is_caught(name, tmp_path):
     mpath.write_text(src.replace(old, new))
     lib = oracle.load(oracle.build(str(mpath), str(tmp_path / "libmutant.so")))
     caught = []
-    for pin in pins.ALL_PINS + nbd_pins.ALL_NBD_PINS + filter_pins.ALL_FILTER_PINS:
+    for pin in (pins.ALL_PINS + nbd_pins.ALL_NBD_PINS + filter_pins.ALL_FILTER_PINS +
+                map_pins.ALL_MAP_PINS):
         try:
             pin(lib)
         except Exception as err:  # any failure of a pin counts as catching the mutant
