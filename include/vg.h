@@ -356,6 +356,61 @@ vg_status vg_nbd_decimate(const vg_points *p, int64_t n, const vg_nbd_params *pr
                           vg_nbd_out *out, int64_t *n_keep, int64_t *rounds,
                           const vg_options *o);
 
+/* ---- global voxel map: marking and clearing (the costmap layer's other hot
+ * operation) ----
+ * Sec. II-C: the layer marks the cells of each new cloud as occupied and
+ * clears, as free, the cells inside the sensor's view, on a sparse map of the
+ * whole space (OpenVDB on the CPU in the paper; a GPU map is its future work,
+ * Sec. IV).  Readings:
+ *   - voxels of edge `res` on a grid fixed in the global frame:
+ *     k_a = floor(RN32(p_a * RN32(1/res))), -2^20 <= k_a < 2^20 (points outside,
+ *     or not finite, are skipped); key = (k_x + 2^20) | (k_y + 2^20) << 21 |
+ *     (k_z + 2^20) << 42;
+ *   - mark: every voxel holding a point gets the (non-zero) time stamp;
+ *   - clear: every occupied voxel whose centre lies in the camera frustum is
+ *     freed.  With c_a = RN32(RN32(k_a + 0.5) * res), d_a = RN32(c_a - trans[a])
+ *     and q_j = RN32(RN32(RN32(rot[j] d_0) + RN32(rot[3+j] d_1)) + RN32(rot[6+j] d_2))
+ *     (the centre in the camera frame), inside iff z_near <= q_2 <= z_far,
+ *     -0.5 <= RN32(RN32(fx * RN32(q_0 / q_2)) + cx) <= width - 0.5 and the same
+ *     for v with fy, cy, height;
+ *   - expire: voxels stamped before min_stamp are freed (temporal decay).
+ * Storage: an open-addressing hash table of `capacity` slots (rounded up to a
+ * power of two) in device memory; a freed voxel keeps its slot until
+ * vg_map_compact.  Keep the used slots under about half the capacity: a mark
+ * whose probe runs too long is dropped and reported (vg_map_stats().full,
+ * and VG_ERR_WORKSPACE from vg_map_export).  mark, clear, expire and compact
+ * are asynchronous on `stream`; export and stats wait for it. */
+typedef struct vg_map vg_map;
+
+typedef struct vg_frustum {
+  float rot[9];          /* camera-to-global rotation, row-major */
+  float trans[3];        /* camera position in the global frame */
+  float fx, fy, cx, cy;  /* pinhole intrinsics, pixels */
+  int32_t width, height; /* image size, >= 1 */
+  float z_near, z_far;   /* depth range along the optical axis, z_near <= z_far */
+} vg_frustum;
+
+typedef struct vg_map_info {
+  int64_t capacity, occupied, used_slots;
+  int64_t last_skipped, last_cleared, last_expired;  /* of the last mark / clear / expire */
+  int32_t full;          /* a mark or compaction ran out of probe length */
+} vg_map_info;
+
+vg_status vg_map_create(int64_t capacity, float res, vg_map **map);
+vg_status vg_map_destroy(vg_map *map);
+/* x, y, z: device [n], global frame; stamp >= 1. */
+vg_status vg_map_mark(vg_map *map, const float *x, const float *y, const float *z, int64_t n,
+                      uint32_t stamp, void *stream);
+vg_status vg_map_clear_frustum(vg_map *map, const vg_frustum *f, void *stream);
+vg_status vg_map_expire(vg_map *map, uint32_t min_stamp, void *stream);
+/* Occupied voxels into device arrays keys, stamps (at most cap written, in no
+ * particular order); *n = their number (host). */
+vg_status vg_map_export(vg_map *map, uint64_t *keys, uint32_t *stamps, int64_t cap, int64_t *n,
+                        void *stream);
+/* Rebuilds the table with its occupied voxels only (freed slots reclaimed). */
+vg_status vg_map_compact(vg_map *map, void *stream);
+vg_status vg_map_stats(vg_map *map, vg_map_info *info, void *stream);
+
 /* ---- a call that allocates nothing ----
  * For callers that cannot allocate: code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc.  The operation of

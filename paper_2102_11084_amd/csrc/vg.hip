@@ -13,6 +13,7 @@
 #include "vg_pipeline.hpp"
 #include "vg_nbd.hpp"
 #include "vg_sparse.hpp"
+#include "vg_map.hpp"
 
 namespace {
 
@@ -1270,6 +1271,184 @@ vg_status vg_batch_plan_destroy(vg_batch_plan* P) {
   if (P->ws_base) (void)hipFree(P->ws_base);
   delete[] P->invs;
   delete P;
+  return VG_OK;
+}
+
+}  // extern "C"
+
+// ============================================================ voxel map ====
+struct vg_map {
+  MapWs ws;
+  void* mem;
+  int64_t cap;
+  uint32_t* host;  // pinned readback
+};
+
+namespace {
+
+int map_grid(uint64_t items) {
+  return (int)std::max<uint64_t>(1, std::min<uint64_t>((items + kMapBlock - 1) / kMapBlock, 8192));
+}
+
+bool frustum_ok(const vg_frustum* f) {
+  for (int k = 0; k < 9; ++k)
+    if (!std::isfinite(f->rot[k])) return false;
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(f->trans[k])) return false;
+  const float v[6] = {f->fx, f->fy, f->cx, f->cy, f->z_near, f->z_far};
+  for (float x : v)
+    if (!std::isfinite(x)) return false;
+  return f->width >= 1 && f->height >= 1 && f->z_near <= f->z_far;
+}
+
+// Sync read of n counters of the map's control block (from index i0).
+vg_status map_read(vg_map* m, int i0, int n, hipStream_t s) {
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(m->ws.ctl) + i0;
+  if (hipMemcpyAsync(m->host, src, 4 * (size_t)n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return VG_ERR_DEVICE;
+  return VG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vg_status vg_map_create(int64_t capacity, float res, vg_map** map) {
+  if (!map) return VG_ERR_ARG;
+  *map = nullptr;
+  if (capacity < 1 || capacity > ((int64_t)1 << 31)) return VG_ERR_ARG;
+  float inv;
+  if (!leaf_inverse(res, &inv)) return VG_ERR_LEAF;
+  int64_t cap = 1024;
+  while (cap < capacity) cap <<= 1;
+  vg_map* m = new (std::nothrow) vg_map();
+  if (!m) return VG_ERR_DEVICE;
+  const size_t bytes = align_up(sizeof(MapCtl)) + (size_t)cap * (8 + 4 + 8 + 4);
+  if (hipMalloc(&m->mem, bytes) != hipSuccess) {
+    delete m;
+    return VG_ERR_DEVICE;
+  }
+  if (hipHostMalloc(reinterpret_cast<void**>(&m->host), 64, hipHostMallocDefault) != hipSuccess) {
+    (void)hipFree(m->mem);
+    delete m;
+    return VG_ERR_DEVICE;
+  }
+  char* b = static_cast<char*>(m->mem);
+  m->ws.ctl = reinterpret_cast<MapCtl*>(b);
+  size_t o = align_up(sizeof(MapCtl));
+  m->ws.keys = reinterpret_cast<uint64_t*>(b + o);    o += 8 * (size_t)cap;
+  m->ws.tkeys = reinterpret_cast<uint64_t*>(b + o);   o += 8 * (size_t)cap;
+  m->ws.stamps = reinterpret_cast<uint32_t*>(b + o);  o += 4 * (size_t)cap;
+  m->ws.tstamps = reinterpret_cast<uint32_t*>(b + o);
+  m->ws.mask = (uint64_t)cap - 1;
+  m->ws.res = res;
+  m->ws.inv = inv;
+  m->cap = cap;
+  hipLaunchKernelGGL(vg_map_reset_kernel, dim3(map_grid(cap)), dim3(kMapBlock), 0, nullptr, m->ws);
+  if (hipMemsetAsync(m->ws.ctl, 0, sizeof(MapCtl), nullptr) != hipSuccess ||
+      hipStreamSynchronize(nullptr) != hipSuccess) {
+    vg_map_destroy(m);
+    return VG_ERR_DEVICE;
+  }
+  *map = m;
+  return VG_OK;
+}
+
+vg_status vg_map_destroy(vg_map* m) {
+  if (!m) return VG_ERR_ARG;
+  (void)hipDeviceSynchronize();
+  if (m->host) (void)hipHostFree(m->host);
+  if (m->mem) (void)hipFree(m->mem);
+  delete m;
+  return VG_OK;
+}
+
+vg_status vg_map_mark(vg_map* m, const float* x, const float* y, const float* z, int64_t n,
+                      uint32_t stamp, void* stream) {
+  if (!m || n < 0 || stamp == 0) return VG_ERR_ARG;
+  if (n > 0 && (!x || !y || !z)) return VG_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(vg_map_zero_kernel, dim3(1), dim3(64), 0, s, &m->ws.ctl->skipped);
+  if (n > 0)
+    hipLaunchKernelGGL(vg_map_mark_kernel, dim3(map_grid((uint64_t)n)), dim3(kMapBlock), 0, s,
+                       m->ws, x, y, z, n, stamp);
+  return hipGetLastError() == hipSuccess ? VG_OK : VG_ERR_DEVICE;
+}
+
+vg_status vg_map_clear_frustum(vg_map* m, const vg_frustum* f, void* stream) {
+  if (!m || !f || !frustum_ok(f)) return VG_ERR_ARG;
+  MapFrustum fr;
+  for (int k = 0; k < 9; ++k) fr.r[k] = f->rot[k];
+  for (int k = 0; k < 3; ++k) fr.t[k] = f->trans[k];
+  fr.fx = f->fx;
+  fr.fy = f->fy;
+  fr.cx = f->cx;
+  fr.cy = f->cy;
+  fr.width = f->width;
+  fr.height = f->height;
+  fr.z_near = f->z_near;
+  fr.z_far = f->z_far;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(vg_map_zero_kernel, dim3(1), dim3(64), 0, s, &m->ws.ctl->cleared);
+  hipLaunchKernelGGL(vg_map_clear_kernel, dim3(map_grid((uint64_t)m->cap)), dim3(kMapBlock), 0, s,
+                     m->ws, fr);
+  return hipGetLastError() == hipSuccess ? VG_OK : VG_ERR_DEVICE;
+}
+
+vg_status vg_map_expire(vg_map* m, uint32_t min_stamp, void* stream) {
+  if (!m) return VG_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(vg_map_zero_kernel, dim3(1), dim3(64), 0, s, &m->ws.ctl->expired);
+  hipLaunchKernelGGL(vg_map_expire_kernel, dim3(map_grid((uint64_t)m->cap)), dim3(kMapBlock), 0, s,
+                     m->ws, min_stamp);
+  return hipGetLastError() == hipSuccess ? VG_OK : VG_ERR_DEVICE;
+}
+
+vg_status vg_map_export(vg_map* m, uint64_t* keys, uint32_t* stamps, int64_t cap, int64_t* n,
+                        void* stream) {
+  if (n) *n = 0;
+  if (!m || !n || cap < 0 || (cap > 0 && (!keys || !stamps))) return VG_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(vg_map_zero_kernel, dim3(1), dim3(64), 0, s, &m->ws.ctl->live);
+  hipLaunchKernelGGL(vg_map_export_kernel, dim3(map_grid((uint64_t)m->cap)), dim3(kMapBlock), 0, s,
+                     m->ws, keys, stamps, (uint64_t)cap);
+  if (hipGetLastError() != hipSuccess) return VG_ERR_DEVICE;
+  const vg_status rc = map_read(m, 0, 5, s);
+  if (rc != VG_OK) return rc;
+  *n = m->host[4];
+  return m->host[0] ? VG_ERR_WORKSPACE : VG_OK;
+}
+
+vg_status vg_map_compact(vg_map* m, void* stream) {
+  if (!m) return VG_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int g = map_grid((uint64_t)m->cap);
+  hipLaunchKernelGGL(vg_map_zero_kernel, dim3(1), dim3(64), 0, s, &m->ws.ctl->live);
+  hipLaunchKernelGGL(vg_map_export_kernel, dim3(g), dim3(kMapBlock), 0, s, m->ws, m->ws.tkeys,
+                     m->ws.tstamps, (uint64_t)m->cap);
+  hipLaunchKernelGGL(vg_map_reset_kernel, dim3(g), dim3(kMapBlock), 0, s, m->ws);
+  hipLaunchKernelGGL(vg_map_reinsert_kernel, dim3(g), dim3(kMapBlock), 0, s, m->ws);
+  return hipGetLastError() == hipSuccess ? VG_OK : VG_ERR_DEVICE;
+}
+
+vg_status vg_map_stats(vg_map* m, vg_map_info* info, void* stream) {
+  if (!m || !info) return VG_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(vg_map_zero_kernel, dim3(1), dim3(64), 0, s, &m->ws.ctl->count[0]);
+  hipLaunchKernelGGL(vg_map_zero_kernel, dim3(1), dim3(64), 0, s, &m->ws.ctl->count[1]);
+  hipLaunchKernelGGL(vg_map_count_kernel, dim3(map_grid((uint64_t)m->cap)), dim3(kMapBlock), 0, s,
+                     m->ws, m->ws.ctl->count);
+  if (hipGetLastError() != hipSuccess) return VG_ERR_DEVICE;
+  const vg_status rc = map_read(m, 0, 7, s);
+  if (rc != VG_OK) return rc;
+  info->capacity = m->cap;
+  info->occupied = m->host[5];
+  info->used_slots = m->host[6];
+  info->last_skipped = m->host[1];
+  info->last_cleared = m->host[2];
+  info->last_expired = m->host[3];
+  info->full = m->host[0] ? 1 : 0;
   return VG_OK;
 }
 

@@ -85,6 +85,34 @@ def make_filter(rot=None, trans=None, z_min=-np.inf, z_max=np.inf, min_points=1)
     return f
 
 
+class vg_frustum(ctypes.Structure):
+    _fields_ = [("rot", ctypes.c_float * 9), ("trans", ctypes.c_float * 3), ("fx", ctypes.c_float),
+                ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("z_near", ctypes.c_float),
+                ("z_far", ctypes.c_float)]
+
+
+class vg_map_info(ctypes.Structure):
+    _fields_ = [("capacity", ctypes.c_int64), ("occupied", ctypes.c_int64),
+                ("used_slots", ctypes.c_int64), ("last_skipped", ctypes.c_int64),
+                ("last_cleared", ctypes.c_int64), ("last_expired", ctypes.c_int64),
+                ("full", ctypes.c_int32)]
+
+
+def make_frustum(rot, trans, fx, fy, cx, cy, width, height, z_near, z_far):
+    f = vg_frustum()
+    R = np.asarray(rot, dtype=np.float32).reshape(9)
+    T = np.asarray(trans, dtype=np.float32).reshape(3)
+    for k in range(9):
+        f.rot[k] = float(R[k])
+    for k in range(3):
+        f.trans[k] = float(T[k])
+    f.fx, f.fy, f.cx, f.cy = float(fx), float(fy), float(cx), float(cy)
+    f.width, f.height = int(width), int(height)
+    f.z_near, f.z_far = float(z_near), float(z_far)
+    return f
+
+
 class VGError(RuntimeError):
     def __init__(self, status, where=""):
         self.status = status
@@ -100,7 +128,9 @@ EXPORTS = ["vg_status_string", "vg_default_tuning", "vg_tuning_supported", "vg_w
            "vg_batch_plan_kernel_times", "vg_batch_plan_set_fail_waits", "vg_batch_plan_destroy",
            "vg_downsample_noalloc", "vg_nbd_workspace_bytes", "vg_nbd_decimate",
            "vg_downsample_filtered", "vg_downsample_batched_filtered", "vg_host_alloc",
-           "vg_host_free", "vg_batch_plan_set_host_input"]
+           "vg_host_free", "vg_batch_plan_set_host_input", "vg_map_create", "vg_map_destroy",
+           "vg_map_mark", "vg_map_clear_frustum", "vg_map_expire", "vg_map_export", "vg_map_compact",
+           "vg_map_stats"]
 
 # Largest cloud of vg_downsample_noalloc and the size of its fixed device array.
 NOALLOC_MAX_POINTS = 1048576
@@ -150,6 +180,14 @@ def lib():
         L.vg_host_alloc.argtypes = [ctypes.c_size_t, ctypes.POINTER(P), ctypes.POINTER(P)]
         L.vg_host_free.argtypes = [P]
         L.vg_batch_plan_set_host_input.argtypes = [P, ctypes.c_int]
+        L.vg_map_create.argtypes = [ctypes.c_int64, ctypes.c_float, ctypes.POINTER(P)]
+        L.vg_map_destroy.argtypes = [P]
+        L.vg_map_mark.argtypes = [P, P, P, P, ctypes.c_int64, ctypes.c_uint32, P]
+        L.vg_map_clear_frustum.argtypes = [P, ctypes.POINTER(vg_frustum), P]
+        L.vg_map_expire.argtypes = [P, ctypes.c_uint32, P]
+        L.vg_map_export.argtypes = [P, P, P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), P]
+        L.vg_map_compact.argtypes = [P, P]
+        L.vg_map_stats.argtypes = [P, ctypes.POINTER(vg_map_info), P]
         L.vg_nbd_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int32]
         L.vg_nbd_workspace_bytes.restype = ctypes.c_size_t
         L.vg_nbd_decimate.argtypes = [ctypes.POINTER(vg_points), ctypes.c_int64,
@@ -518,6 +556,78 @@ class BatchPlan:
     def close(self):
         if self._h:
             lib().vg_batch_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class VoxelMap:
+    """Global voxel map on the GPU (vg_map_*): mark a cloud's voxels with a
+    time stamp, clear the voxels in a camera frustum, expire old voxels."""
+
+    def __init__(self, capacity, res):
+        self._h = ctypes.c_void_p()
+        st = lib().vg_map_create(int(capacity), ctypes.c_float(res), ctypes.byref(self._h))
+        if st != VG_OK:
+            raise VGError(st, "vg_map_create")
+
+    @staticmethod
+    def _stream():
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def mark(self, x, y, z, stamp):
+        n = x.numel()
+        for t in (x, y, z):
+            if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.numel() == n):
+                raise ValueError("x, y, z must be contiguous float32 CUDA tensors of equal length")
+        st = lib().vg_map_mark(self._h, _ptr(x), _ptr(y), _ptr(z), n, int(stamp), self._stream())
+        if st != VG_OK:
+            raise VGError(st, "vg_map_mark")
+
+    def clear(self, frustum):
+        st = lib().vg_map_clear_frustum(self._h, ctypes.byref(frustum), self._stream())
+        if st != VG_OK:
+            raise VGError(st, "vg_map_clear_frustum")
+
+    def expire(self, min_stamp):
+        st = lib().vg_map_expire(self._h, int(min_stamp), self._stream())
+        if st != VG_OK:
+            raise VGError(st, "vg_map_expire")
+
+    def compact(self):
+        st = lib().vg_map_compact(self._h, self._stream())
+        if st != VG_OK:
+            raise VGError(st, "vg_map_compact")
+
+    def export(self):
+        """(keys uint64, stamps uint32) of the occupied voxels, sorted by key (numpy)."""
+        info = self.stats()
+        cap = max(int(info.occupied), 1)
+        keys = torch.empty(cap, dtype=torch.int64, device="cuda")
+        stamps = torch.empty(cap, dtype=torch.int32, device="cuda")
+        n = ctypes.c_int64(0)
+        st = lib().vg_map_export(self._h, _ptr(keys), _ptr(stamps), cap, ctypes.byref(n), self._stream())
+        if st != VG_OK:
+            raise VGError(st, "vg_map_export")
+        k = keys[:n.value].cpu().numpy().view(np.uint64)
+        s = stamps[:n.value].cpu().numpy().view(np.uint32)
+        order = np.argsort(k, kind="stable")
+        return k[order], s[order]
+
+    def stats(self):
+        info = vg_map_info()
+        st = lib().vg_map_stats(self._h, ctypes.byref(info), self._stream())
+        if st != VG_OK:
+            raise VGError(st, "vg_map_stats")
+        return info
+
+    def close(self):
+        if self._h:
+            lib().vg_map_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):
