@@ -178,10 +178,11 @@ def kernel_table(per_kind, steps, kbytes):
             for k, v in per_kind.items()}
 
 
-def single_cloud_leg(name, cloud, leaf, tuning, dev, reps, oracle_runs):
+def single_cloud_leg(name, cloud, leaf, tuning, dev, reps, oracle_runs, cpu_jobs):
     """One cloud through the plain path (synchronous vg_downsample_ex calls,
-    m read back), its kernels timed through a one-frame plan, and the oracle
-    on the same cloud."""
+    m read back) and its kernels timed through a one-frame plan; the oracle's
+    timing on the same cloud is registered in cpu_jobs for the CPU-baseline
+    leg."""
     import torch
 
     from paper_2102_11084_amd import vg
@@ -223,14 +224,16 @@ def single_cloud_leg(name, cloud, leaf, tuning, dev, reps, oracle_runs):
         "radix_roofline_frac": round(sort["gbs"] / HBM_PEAK_GBS, 4) if sort and sort["gbs"] else None,
     }
     if oracle_runs > 0:
-        import oracle
-        oracle.load()
-        ot = []
-        for _ in range(oracle_runs):
-            c0 = time.perf_counter()
-            oracle.downsample(x, y, z, rgb, leaf)
-            ot.append(time.perf_counter() - c0)
-        leg["oracle_mpoints_s_1core"] = round(n / float(np.median(ot)) / 1e6, 2)
+        def job(x=x, y=y, z=z, rgb=rgb, leaf=leaf, runs=oracle_runs, n=n):
+            import oracle
+            ot = []
+            for _ in range(runs):
+                c0 = time.perf_counter()
+                oracle.downsample(x, y, z, rgb, leaf)
+                ot.append(time.perf_counter() - c0)
+            return {"mpoints_s": round(n / float(np.median(ot)) / 1e6, 3),
+                    "sample": f"the whole cloud, median of {runs}"}
+        cpu_jobs.append((name, job))
     return leg
 
 
@@ -262,10 +265,11 @@ def nbd_candidate_checks(x, y, z, leaf):
     return int((cnt * s).sum())
 
 
-def nbd_leg(tuning, dev, reps=5, oracle_runs=1):
+def nbd_leg(tuning, dev, reps=5, oracle_runs=1, cpu_jobs=None):
     """The paper's own filter (Alg. 1, neighbour-bucket decimation) on a
     640x480 frame: leaf and radius 0.02 m (the paper's Table I grid),
-    umbral 16, 1000 points per round.  Whole synchronous calls are timed."""
+    umbral 16, 1000 points per round.  Whole synchronous calls are timed; the
+    oracle's timing is registered in cpu_jobs for the CPU-baseline leg."""
     import torch
 
     from paper_2102_11084_amd import datagen as dg
@@ -294,16 +298,17 @@ def nbd_leg(tuning, dev, reps=5, oracle_runs=1):
            "us_per_round": round(med * 1e6 / max(int(r["rounds"]), 1), 2),
            "mpoints_s": round(n / med / 1e6, 2),
            "candidate_pairs": nbd_candidate_checks(x, y, z, leaf)}
-    if oracle_runs > 0:
-        import oracle
-        oracle.load()
-        ot = []
-        for _ in range(oracle_runs):
-            c0 = time.perf_counter()
-            o = oracle.nbd_decimate(x, y, z, leaf, leaf, umbral, seed, rs)
-            ot.append(time.perf_counter() - c0)
-        leg["oracle_ms_1core"] = round(float(np.median(ot)) * 1e3, 1)
-        leg["matches_oracle"] = bool(o["rounds"] == r["rounds"] and int(o["keep"].sum()) == r["n_keep"])
+    if oracle_runs > 0 and cpu_jobs is not None:
+        def job():
+            import oracle
+            ot = []
+            for _ in range(oracle_runs):
+                c0 = time.perf_counter()
+                oracle.nbd_decimate(x, y, z, leaf, leaf, umbral, seed, rs)
+                ot.append(time.perf_counter() - c0)
+            return {"ms_per_frame": round(float(np.median(ot)) * 1e3, 1),
+                    "sample": f"the same frame, median of {oracle_runs}"}
+        cpu_jobs.append((leg["workload"], job))
     return leg
 
 
@@ -381,6 +386,66 @@ def ingest_leg(x, y, z, rgb, offs, leaves, d, plan, outs, o_ref, tuning, dev, st
         "zero_copy_input_gbs": round(in_bytes / (zc_ms * 1e-3) / 1e9, 1),
         "zero_copy_bit_identical": same,
     }
+
+
+def map_leg(fout, fo_offsets, offs, leaves, dev, cpu_jobs, res=0.05, capacity=1 << 22, reps=5):
+    """The costmap layer's map update over the filtered frames: per frame, the
+    voxels inside its camera frustum are cleared, then the frame's cells (in
+    the global frame) are marked with the frame's stamp.  The whole 64-frame
+    sequence is timed on a fresh map each repetition; the oracle's map runs
+    the same sequence in the CPU-baseline leg (cpu_jobs)."""
+    import torch
+
+    from paper_2102_11084_amd import datagen as dg
+    from paper_2102_11084_amd import vg
+    B = len(leaves)
+    fr = []
+    for b in range(B):
+        W, H = int(dg.batch_frame_spec(b)["W"]), int(dg.batch_frame_spec(b)["H"])
+        R, t = dg.camera_pose(8000 + b)
+        f = 525.0 * W / 640.0
+        fr.append((R, t, f, f, (W - 1) / 2.0, (H - 1) / 2.0, W, H, 0.3, 4.0))
+    frus = [vg.make_frustum(*a) for a in fr]
+    lo = [int(fo_offsets[b]) for b in range(B + 1)]
+    cells = [(fout["x"][lo[b]:lo[b + 1]], fout["y"][lo[b]:lo[b + 1]], fout["z"][lo[b]:lo[b + 1]])
+             for b in range(B)]
+    stream = torch.cuda.current_stream(dev)
+    times = []
+    for rep in range(reps + 1):
+        m = vg.VoxelMap(capacity, res)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for b in range(B):
+            m.clear(frus[b])
+            m.mark(*cells[b], b + 1)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if rep > 0:
+            times.append(e0.elapsed_time(e1))
+        info = m.stats()
+        gk, gs = m.export()
+        m.close()
+    ms = float(np.median(times))
+    leg = {"workload": f"{B} filtered frames in order: clear the frame's camera frustum (0.3..4 m), "
+                       f"then mark its cells; voxel {res} m, {capacity} slots",
+           "ms_sequence": round(ms, 3), "ms_per_frame": round(ms / B, 4),
+           "cells_marked": int(lo[B]), "voxels_at_end": int(info.occupied),
+           "slots_used": int(info.used_slots)}
+    host_cells = [tuple(c.cpu().numpy() for c in cb) for cb in cells]
+
+    def job():
+        import oracle
+        o = oracle.VoxelMap(res)
+        c0 = time.perf_counter()
+        for b in range(B):
+            o.clear(*fr[b])
+            o.mark(*host_cells[b], b + 1)
+        ms = (time.perf_counter() - c0) * 1e3
+        o.close()
+        return {"ms_sequence": round(ms, 1), "sample": "the same 64-frame sequence, once"}
+    cpu_jobs.append((leg["workload"], job))
+    return leg
 
 
 def main():
@@ -542,6 +607,7 @@ def main():
         "kernels": kinds,
     }
 
+    cpu_jobs = []  # oracle timings of the legs' workloads, run in the CPU-baseline leg
     if not args.no_legs:
         # plain per-frame path: one synchronous vg_downsample_ex per frame
         ws = torch.empty(vg.workspace_bytes(int(np.diff(offs).max()), 1, tuning), dtype=torch.uint8,
@@ -638,6 +704,8 @@ def main():
         torch.cuda.synchronize()
         fms = f0.elapsed_time(f1) / args.steps
         fo = {k: v.cpu().numpy() for k, v in fouts[0].items() if k in ("out_offsets", "frame_status", "count")}
+        result["legs"]["voxel_map"] = map_leg(fouts[0], fo["out_offsets"], offs, leaves, dev, cpu_jobs)
+        log(f"leg: voxel map: {result['legs']['voxel_map']['ms_per_frame']} ms per frame")
         fplan.close()
         assert (fo["frame_status"] == 0).all(), "a filtered frame failed"
         kept = int(fo["count"][:int(fo["out_offsets"][-1])].astype(np.int64).sum())
@@ -657,20 +725,31 @@ def main():
         if not args.no_config_legs:
             cfg = []
             cfg.append(single_cloud_leg("640x480 RGB-D frame, plain path", dg.frame_640x480(), 0.05,
-                                        tuning, dev, 30, 3))
+                                        tuning, dev, 30, 3, cpu_jobs))
             log(f"leg: {cfg[-1]['workload']}: {cfg[-1]['mpoints_s']} Mpoints/s")
             f720 = dg.frame_1280x720()
             for leaf in (0.01, 0.02, 0.05, 0.10):
                 cfg.append(single_cloud_leg(f"1280x720 RGB-D frame, leaf {leaf}, plain path", f720,
-                                            leaf, tuning, dev, 30, 3))
+                                            leaf, tuning, dev, 30, 3, cpu_jobs))
                 log(f"leg: {cfg[-1]['workload']}: {cfg[-1]['mpoints_s']} Mpoints/s")
             room = dg.room_map()
             cfg.append(single_cloud_leg("16M-point shuffled room map, leaf 0.02, plain path", room,
-                                        0.02, tuning, dev, 10, 1))
+                                        0.02, tuning, dev, 10, 0, cpu_jobs))
             log(f"leg: {cfg[-1]['workload']}: {cfg[-1]['mpoints_s']} Mpoints/s")
+            # the oracle on a bounded sample of the map: its first 4M points (the
+            # points are shuffled, so any 4M of them are a uniform sample)
+            sub = tuple(np.ascontiguousarray(a[:4_000_000]) for a in room)
+
+            def room_job(sub=sub):
+                import oracle
+                c0 = time.perf_counter()
+                oracle.downsample(sub[0], sub[1], sub[2], sub[3], 0.02)
+                return {"mpoints_s": round(4_000_000 / (time.perf_counter() - c0) / 1e6, 3),
+                        "sample": "the map's first 4,000,000 (shuffled) points, once"}
+            cpu_jobs.append((cfg[-1]["workload"], room_job))
             del room
             result["legs"]["configs"] = cfg
-            result["legs"]["nbd_decimation"] = nbd_leg(tuning, dev)
+            result["legs"]["nbd_decimation"] = nbd_leg(tuning, dev, cpu_jobs=cpu_jobs)
             log(f"leg: decimation: {result['legs']['nbd_decimation']['ms_median']} ms per frame, "
                 f"{result['legs']['nbd_decimation']['rounds']} rounds")
 
@@ -708,6 +787,12 @@ def main():
             "runs_mpoints_s": [round(r[0], 3) for r in runs],
             "host_cpu": _cpu_name(), "host_cores_available": len(cpus),
         }
+        # the oracle on the legs' workloads (same pinned core)
+        os.sched_setaffinity(0, {core})
+        try:
+            result["cpu_baseline"]["legs"] = {name: job() for name, job in cpu_jobs}
+        finally:
+            os.sched_setaffinity(0, set(cpus))
         log(f"cpu oracle: {result['cpu_baseline']['value']} Mpoints/s on 1 core")
 
     plan.close()
