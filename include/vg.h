@@ -126,7 +126,9 @@ const char *vg_status_string(vg_status s);
  * after Alg. 1; the tuning generalises that choice.) */
 vg_status vg_default_tuning(vg_tuning *t);
 
-/* VG_OK if the library holds kernels for this tuning, else VG_ERR_ARG.
+/* VG_OK if the library holds kernels for this tuning, else VG_ERR_ARG.  The
+ * VG_EXEC_PERSISTENT form is built for the variants with 4 reduce items per
+ * thread only (512/8/8/4 and 256/8/8/4).
  * (Library helper; not in the paper.) */
 vg_status vg_tuning_supported(const vg_tuning *t);
 

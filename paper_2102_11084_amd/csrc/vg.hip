@@ -43,10 +43,11 @@ void launch_kind(const Ws& ws, int lo, int hi, int cus, int bpc, hipStream_t s) 
 // Launches phases [lo, hi): all of them in one persistent kernel, or one phase
 // with the kernel compiled for that phase kind.  Grids are fixed per kernel
 // (CUs x resident workgroups), independent of the call's sizes.
-template <class C>
+template <class C, bool ONE>
 void launch_pipeline(const Ws& ws, int lo, int hi, int cus, int bpc, hipStream_t s) {
-  if (lo == 0 && hi == C::NPH) launch_kind<C, kAll>(ws, lo, hi, cus, bpc, s);
-  else if (lo == C::PH_BBOX) launch_kind<C, kBbox>(ws, lo, hi, cus, bpc, s);
+  if (lo == 0 && hi == C::NPH) {
+    if constexpr (ONE) launch_kind<C, kAll>(ws, lo, hi, cus, bpc, s);
+  } else if (lo == C::PH_BBOX) launch_kind<C, kBbox>(ws, lo, hi, cus, bpc, s);
   else if (lo == C::PH_HIST) launch_kind<C, kHist>(ws, lo, hi, cus, bpc, s);
   else if (lo == C::PH_RED) launch_kind<C, kRed>(ws, lo, hi, cus, bpc, s);
   else if (lo == C::PH_FIX) launch_kind<C, kFix>(ws, lo, hi, cus, bpc, s);
@@ -56,21 +57,25 @@ void launch_pipeline(const Ws& ws, int lo, int hi, int cus, int bpc, hipStream_t
 struct Variant {
   int block, sort_items, radix, red_items;
   int nph, maxp, R, TS, TB, TR, ph_red;
+  bool one;  // built with the one-launch (persistent) form too
   void (*launch)(const Ws&, int ph_lo, int ph_hi, int cus, int bpc, hipStream_t);
 };
 
-template <int B, int SI, int W, int RI>
+template <int B, int SI, int W, int RI, bool ONE = false>
 constexpr Variant make_variant() {
   using C = Cfg<B, SI, W, RI>;
-  return Variant{B, SI, W, RI, C::NPH, C::MAXP, C::R, C::TS, C::TB, C::TR, C::PH_RED,
-                 &launch_pipeline<C>};
+  return Variant{B, SI, W, RI, C::NPH, C::MAXP, C::R, C::TS, C::TB, C::TR, C::PH_RED, ONE,
+                 &launch_pipeline<C, ONE>};
 }
 
 // Built variants: (threads, sort items/thread, radix bits, reduce items/thread).
+// The one-launch form, whose kernel holds every phase's registers at once, is
+// built only where that kernel needs no scratch memory (4 reduce items per
+// thread); the others spill their per-thread arrays to 576 B of scratch a lane.
 const Variant kVariants[] = {
     make_variant<256, 16, 8, 8>(), make_variant<256, 8, 8, 8>(),  make_variant<256, 12, 8, 8>(),
-    make_variant<256, 16, 8, 4>(), make_variant<256, 16, 7, 8>(), make_variant<512, 8, 8, 4>(),
-    make_variant<512, 8, 8, 8>(),  make_variant<256, 16, 6, 8>(), make_variant<256, 8, 8, 4>(),
+    make_variant<256, 16, 8, 4>(), make_variant<256, 16, 7, 8>(), make_variant<512, 8, 8, 4, true>(),
+    make_variant<512, 8, 8, 8>(),  make_variant<256, 16, 6, 8>(), make_variant<256, 8, 8, 4, true>(),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -85,7 +90,7 @@ const Variant* find_variant(const vg_tuning* t) {
     const Variant& v = kVariants[i];
     if (v.block == t->sort_block && v.sort_items == t->sort_items && v.radix == t->radix_bits &&
         v.red_items == t->reduce_items)
-      return &v;
+      return (t->exec_mode == VG_EXEC_PERSISTENT && !v.one) ? nullptr : &v;
   }
   return nullptr;
 }

@@ -209,6 +209,15 @@ def default_tuning(**over) -> vg_tuning:
     return t
 
 
+def launch_tuning(exec_mode: int) -> vg_tuning:
+    """A built tuning for the given launch form: the default for the phased
+    form, the default's shape with 4 reduce items per thread for the one-launch
+    form (the shapes it is built for)."""
+    if exec_mode == EXEC_PERSISTENT:
+        return default_tuning(reduce_items=4, exec_mode=EXEC_PERSISTENT)
+    return default_tuning(exec_mode=exec_mode)
+
+
 def load_tuning(path: str) -> vg_tuning:
     """Tuning written by the autotuner (JSON object with vg_tuning's fields)."""
     import json

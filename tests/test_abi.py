@@ -150,3 +150,11 @@ def test_filter_arguments_rejected_before_any_launch():
     assert L.vg_downsample_filtered(ctypes.byref(pts), 10, ctypes.c_float(0.1), None,
                                     ctypes.byref(cells), ctypes.byref(m),
                                     ctypes.byref(opts)) == vg.VG_ERR_ARG
+
+
+def test_one_launch_form_only_where_built():
+    # the one-launch form is built for the shapes with 4 reduce items per thread
+    assert vg.tuning_supported(vg.default_tuning(reduce_items=4, exec_mode=vg.EXEC_PERSISTENT))
+    assert not vg.tuning_supported(vg.default_tuning(exec_mode=vg.EXEC_PERSISTENT))
+    assert vg.tuning_supported(vg.launch_tuning(vg.EXEC_PERSISTENT))
+    assert vg.tuning_supported(vg.launch_tuning(vg.EXEC_PHASED))

@@ -79,7 +79,7 @@ def test_small_batch_matches_per_frame_oracle(key_mode):
 @pytest.mark.parametrize("mode", [vg.EXEC_PERSISTENT, vg.EXEC_PHASED])
 def test_batched_equals_plain_bitwise(mode):
     x, y, z, rgb, offs, leaves = small_batch(seed=1)
-    t = vg.default_tuning(exec_mode=mode)
+    t = vg.launch_tuning(mode)
     g = run_batched(x, y, z, rgb, offs, leaves, tuning=t)
     for b in range(len(leaves)):
         s0, s1 = int(offs[b]), int(offs[b + 1])
@@ -124,7 +124,7 @@ def test_timed_launches_match_graph_replay(mode):
     bytes as graph replay, and names every launch of the call in order."""
     print(f"case timed launches, exec mode {mode}", flush=True)
     x, y, z, rgb, offs, leaves = small_batch(seed=6)
-    t = vg.default_tuning(exec_mode=mode)
+    t = vg.launch_tuning(mode)
     plan = vg.BatchPlan(16, 400_000, vg.KEY_LINEAR, t, use_graph=True)
     gg = run_batched(x, y, z, rgb, offs, leaves, plan=plan)
     plan.set_timing(True)
@@ -205,7 +205,7 @@ def test_device_timeout_marks_every_frame(mode, use_graph):
     call is correct again."""
     print(f"case simulated time-out, exec mode {mode}, graph {use_graph}", flush=True)
     x, y, z, rgb, offs, leaves = small_batch(seed=7)
-    t = vg.default_tuning(exec_mode=mode)
+    t = vg.launch_tuning(mode)
     plan = vg.BatchPlan(16, 400_000, vg.KEY_LINEAR, t, use_graph=use_graph)
     good = run_batched(x, y, z, rgb, offs, leaves, plan=plan)
     check_against_oracle(good, x, y, z, rgb, offs, leaves)

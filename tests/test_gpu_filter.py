@@ -124,7 +124,7 @@ def _check_batch(g, cat, offs, leaves, kws):
 def test_batched_filtered_matches_per_frame_oracle(mode, use_graph):
     print(f"case filtered batch, exec mode {mode}, graph {use_graph}", flush=True)
     cat, offs, leaves, kws = _batch(5)
-    t = vg.default_tuning(exec_mode=mode)
+    t = vg.launch_tuning(mode)
     plan = vg.BatchPlan(len(leaves), int(offs[-1]), vg.KEY_LINEAR, t, use_graph=use_graph)
     d = to_dev(cat[0], cat[1], cat[2], cat[3].reshape(-1))
     # an unfiltered call first (a graph then lacks the sparse-cell pass), then

@@ -43,7 +43,7 @@ def test_host_input_bit_identical(mode, use_graph):
     print(f"case host input, exec mode {mode}, graph {use_graph}", flush=True)
     x, y, z, rgb, offs, leaves = small_batch(seed=11)
     n = x.size
-    t = vg.default_tuning(exec_mode=mode)
+    t = vg.launch_tuning(mode)
     dev_plan = vg.BatchPlan(len(leaves), n, vg.KEY_LINEAR, t, use_graph=use_graph)
     ref = host(dev_plan.run(*to_dev(x, y, z, rgb.reshape(-1)), offs, leaves))
     torch.cuda.synchronize()
