@@ -472,7 +472,7 @@ def main():
                     help="steps of the per-kernel event timing region")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and exit")
-    ap.add_argument("--leg", choices=["nbd"], default=None,
+    ap.add_argument("--leg", choices=["nbd", "room"], default=None,
                     help="only run the named leg (without its oracle timing) and print its JSON; "
                          "for profiling")
     args = ap.parse_args()
@@ -495,6 +495,11 @@ def main():
     tuning = vg.load_tuning(args.tuning) if os.path.exists(args.tuning) else vg.default_tuning()
     if args.leg == "nbd":
         print(json.dumps(nbd_leg(tuning, dev, reps=max(args.steps, 1), oracle_runs=0)), flush=True)
+        return
+    if args.leg == "room":
+        leg = single_cloud_leg("16M-point shuffled room map, leaf 0.02, plain path", dg.room_map(),
+                               0.02, tuning, dev, max(args.steps, 1), 0, [])
+        print(json.dumps(leg), flush=True)
         return
     if args.exec_mode != "tuned":
         tuning.exec_mode = vg.EXEC_PHASED if args.exec_mode == "phased" else vg.EXEC_PERSISTENT

@@ -702,7 +702,7 @@ __device__ __forceinline__ void bbox_batch(const Ws& ws, const GIo& io, BboxAcc&
 // End of a bbox tile: block reduction, frame atomics, done counter.
 template <class C>
 __device__ __forceinline__ void bbox_finish(const Ws& ws, typename C::BboxSmem& bs, BboxAcc& a,
-                                            int b, bool persistent) {
+                                            int b, bool persistent, uint32_t tiles = 1u) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -735,7 +735,7 @@ __device__ __forceinline__ void bbox_finish(const Ws& ws, typename C::BboxSmem& 
       atomicAdd(&fs->n_valid, tn);
     }
     if (persistent) fence_rel();
-    atomicAdd(&fs->bbox_done, 1u);
+    atomicAdd(&fs->bbox_done, tiles);
   }
   __syncthreads();  // bs is reused by the next tile
 }
@@ -863,7 +863,8 @@ __device__ __forceinline__ void hist_batch(const Ws& ws, const GIo& io, typename
 // are cleared for the next tile), then the done counters.
 template <class C>
 __device__ __forceinline__ void hist_finish(const Ws& ws, typename C::HistSmem& hs, int b,
-                                            const FrameParams& f, bool persistent) {
+                                            const FrameParams& f, bool persistent,
+                                            uint32_t tiles = 1u) {
   const int P = f.status == kFrameOverflow ? 0 : f.passes;
   __syncthreads();
   for (int i = threadIdx.x; i < P * C::R; i += C::BLOCK) {
@@ -878,8 +879,8 @@ __device__ __forceinline__ void hist_finish(const Ws& ws, typename C::HistSmem& 
   if (threadIdx.x == 0) {
     if (P > 0) atomicMax(&ws.ctl->max_passes, (uint32_t)P);
     if (persistent) fence_rel();
-    atomicAdd(&ws.fs[b].hist_done, 1u);
-    atomicAdd(&ws.ctl->hist_tiles_done, 1u);
+    atomicAdd(&ws.fs[b].hist_done, tiles);
+    atomicAdd(&ws.ctl->hist_tiles_done, tiles);
   }
 }
 
@@ -905,12 +906,18 @@ __device__ void hist_tile(const Ws& ws, const GIo& io, typename C::HistSmem& hs,
 
 // Big tiles of a one-phase bbox or histogram launch (frames cached in LDS,
 // at least one point in the call).  These tiles wait on nothing, so tile t
-// goes to workgroup t mod G without a queue, and each workgroup streams its
-// tiles' points: the next batch (of this tile or of the workgroup's next tile)
-// is requested before the current one is processed.  That request is made on
-// every iteration (of point 0 when there is no next batch), so the number of
-// loads in flight is the same on every path and the wait for the current
-// batch does not drain the next one.
+// goes to workgroup t mod G without a queue (the workgroups read neighbouring
+// tiles at any one time; runs of consecutive tiles per workgroup measured
+// slower), and each workgroup streams its tiles' points: the next batch (of
+// this tile or of the workgroup's next tile) is requested before the current
+// one is processed.  That request is made on every iteration (of point 0 when
+// there is no next batch), so the number of loads in flight is the same on
+// every path and the wait for the current batch does not drain the next one.
+// A workgroup's successive tiles of one frame (a cloud of more than G tiles)
+// share one accumulation (box, LDS histogram), handed to the frame's totals
+// when the frame changes or the tiles run out: one set of frame atomics per
+// frame and workgroup, not per tile, which a single large cloud would
+// otherwise queue by the thousand on one line.
 template <class C, int KIND, bool RGB, bool XF = false>
 __device__ void stream_big_tiles(const Ws& ws, const GIo& io, const CallHdr& hdr, BlockCtl& bc,
                                  typename SmemOf<C, KIND>::type& sm) {
@@ -934,6 +941,7 @@ __device__ void stream_big_tiles(const Ws& ws, const GIo& io, const CallHdr& hdr
   };
   int t = blockIdx.x;
   if (t >= NT) return;
+  uint32_t ntl = 0;  // tiles accumulated since the last hand-over
   int b = frame_of(t);
   int64_t t0 = (int64_t)(t - (int)__builtin_amdgcn_readfirstlane(bc.tp[0][b])) * C::TB;
   int64_t off = wave_uniform(bc.fda[b].off), fn = wave_uniform(bc.fda[b].n);
@@ -975,16 +983,24 @@ __device__ void stream_big_tiles(const Ws& ws, const GIo& io, const CallHdr& hdr
       else hist_batch<C, HB>(ws, io, sm.hist, f, hdr.key_mode, cur, off + t0 + c, cnt - c, hdr.want);
     }
     if (t2 != t) {
+      ++ntl;
+      const bool hand_over = t2 >= NT || b2 != b;
       if constexpr (KIND == kBbox) {
-        bbox_finish<C>(ws, sm.bbox, acc, b, false);
-        bbox_zero(acc);
-        if constexpr (XF) {
-          if (t2 < NT) fx = wave_uniform(ws.xf[b2]);
+        if (hand_over) {
+          bbox_finish<C>(ws, sm.bbox, acc, b, false, ntl);
+          bbox_zero(acc);
+          ntl = 0;
+          if constexpr (XF) {
+            if (t2 < NT) fx = wave_uniform(ws.xf[b2]);
+          }
         }
       } else {
-        hist_finish<C>(ws, sm.hist, b, f, false);
+        if (hand_over) {
+          hist_finish<C>(ws, sm.hist, b, f, false, ntl);
+          ntl = 0;
+        }
         if (t2 < NT) {
-          f = wave_uniform(bc.fpa[b2]);
+          if (hand_over) f = wave_uniform(bc.fpa[b2]);
           hist_start<C>(ws, bc.fda[b2], (int)(t02 / C::TB), f);
         }
       }
