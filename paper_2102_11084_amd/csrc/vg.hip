@@ -686,7 +686,7 @@ namespace {
 
 struct NbdLayout {
   size_t ckey, ccount, pcell, ctl, seg, cursor, bsum, sx, sy, sz, sidx, scell, rng, cnt, alive,
-      mflag, partial, cand, del, mlog, keep, kpos, total;
+      cand, del, mlog, keep, kpos, total;
   uint32_t log_cap;
   int scan_blocks;
 };
@@ -714,8 +714,6 @@ NbdLayout make_nbd_layout(size_t o, int64_t n, int64_t round_size) {
   L.rng = o;    o = align_up(o + 8 * 9 * N);
   L.cnt = o;    o = align_up(o + 4 * N);
   L.alive = o;  o = align_up(o + N);
-  L.mflag = o;  o = align_up(o + N);
-  L.partial = o; o = align_up(o + 4 * (size_t)kNbdMarkBlocks);
   L.cand = o;   o = align_up(o + sizeof(NbdCand) * N);
   L.del = o;    o = align_up(o + 4 * K);
   L.mlog = o;   o = align_up(o + 8 * (size_t)L.log_cap);
@@ -811,8 +809,6 @@ vg_status vg_nbd_decimate(const vg_points* p, int64_t n, const vg_nbd_params* pr
   w.rng = reinterpret_cast<uint2*>(b + NL.rng);
   w.cnt = reinterpret_cast<uint32_t*>(b + NL.cnt);
   w.alive = reinterpret_cast<uint8_t*>(b + NL.alive);
-  w.mflag = reinterpret_cast<uint8_t*>(b + NL.mflag);
-  w.partial = reinterpret_cast<uint32_t*>(b + NL.partial);
   w.cand = reinterpret_cast<NbdCand*>(b + NL.cand);
   w.del = reinterpret_cast<uint32_t*>(b + NL.del);
   w.marked_log = reinterpret_cast<int64_t*>(b + NL.mlog);
@@ -866,18 +862,15 @@ vg_status vg_nbd_decimate(const vg_points* p, int64_t n, const vg_nbd_params* pr
     hipLaunchKernelGGL(nbd_ranges_kernel, dim3(gp), dim3(kNbdBlock), 0, s, w);
     hipLaunchKernelGGL(nbd_count_kernel, dim3(gp), dim3(kNbdBlock), 0, s, w);
     // 3. rounds, enqueued in batches ahead of the host's look at the done flag
-    const int gm = grid_for(n, kNbdBlock, kNbdMarkBlocks);
-    const int gr = grid_for(n, kNbdBlock, 2048);
+    //    (the round kernel's LDS allows one workgroup per CU)
+    const int gr = grid_for(n, kPickBlock, cus);
     const int gd = grid_for(std::min<int64_t>(prm->round_size, n), kNbdBlock / 64, 2048);
     const int64_t max_rounds = n / prm->round_size + 2;
     int64_t issued = 0;
     int batch = 4;
     for (;;) {
       for (int r = 0; r < batch; ++r) {
-        hipLaunchKernelGGL(nbd_mark_kernel, dim3(gm), dim3(kNbdBlock), 0, s, w);
-        hipLaunchKernelGGL(nbd_select_kernel, dim3(1), dim3(1024), 0, s, w, (uint32_t)gm);
-        hipLaunchKernelGGL(nbd_collect_kernel, dim3(gr), dim3(kNbdBlock), 0, s, w);
-        hipLaunchKernelGGL(nbd_pick_kernel, dim3(1), dim3(kPickBlock), 0, s, w);
+        hipLaunchKernelGGL(nbd_round_kernel, dim3(gr), dim3(kPickBlock), 0, s, w);
         hipLaunchKernelGGL(nbd_decrement_kernel, dim3(gd), dim3(kNbdBlock), 0, s, w);
       }
       issued += batch;

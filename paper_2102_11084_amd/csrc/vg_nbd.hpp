@@ -10,18 +10,20 @@
 //             run is one range of bucket-ordered points): the 27-bucket search
 //   count     per point, its neighbours: points of the 9 ranges within the
 //             radius (Eq. (1), in binary32 with one rounding per operation)
-// and then rounds (Alg. 1's loop), each five launches:
-//   mark      points present with more than `umbral` neighbours are flagged;
-//             each workgroup counts its flags
-//   select    (one workgroup) the round's marked count; if at most round_size
-//             this is the last round; else a priority window expected to hold
-//             the round_size smallest priorities (with a wide margin)
-//   collect   in the last round every marked point is deleted; otherwise the
-//             marked points in the window become candidates
-//   pick      (one workgroup) the round_size candidates of smallest (priority,
-//             index), each ranked against the others in LDS, are deleted (an
-//             exact radix select over every marked point when the window
-//             falls short); the round counter advances
+// and then rounds (Alg. 1's loop), each two launches:
+//   round     the round's marked points are those present with more than
+//             `umbral` neighbours.  An upper bound of their number (the last
+//             round's count less its deletions: counts only fall) tells every
+//             workgroup at once whether this is surely the last round (every
+//             marked point is deleted) or else the priority window expected to
+//             hold the round_size smallest priorities (with a wide margin); the
+//             marked points in the window become candidates, and each
+//             workgroup counts the marked points it saw.  The workgroup that
+//             finishes last then has the exact count and picks: the round_size
+//             candidates of smallest (priority, index), each ranked against the
+//             others in LDS, are deleted (an exact radix select over every
+//             marked point when the window falls short; every marked point when
+//             there are at most round_size); the round counter advances
 //   decrement the neighbours of every point deleted in the round lose one
 //             from their count (no recount: a count only ever changes by the
 //             deletions around it)
@@ -35,7 +37,6 @@
 namespace vg {
 
 constexpr int kNbdBlock = 256;
-constexpr int kNbdMarkBlocks = 1024;    // workgroups of the mark launch
 
 struct NbdCtl {
   float mn[3];
@@ -51,10 +52,10 @@ struct NbdCtl {
   uint64_t seed;
   uint32_t round;       // rounds finished
   uint32_t done;        // the last round has run
-  uint32_t last;        // the current round is the last one
-  uint32_t marked;      // points marked in the current round
+  uint32_t marked;      // at least the points marked at the start of the next round
   uint32_t ncand;       // candidates of the current round
-  uint32_t ndel;        // points deleted in the current round
+  uint32_t ndel;        // points deleted in the current round (appends)
+  uint32_t ndel_out;    // points deleted in the round just picked (for the decrement)
   uint32_t bstar;       // priority bucket of the round_size-th smallest
   uint32_t need;        // candidates still to delete from that bucket
   uint32_t n_in;        // length of the keep scan's input
@@ -62,11 +63,13 @@ struct NbdCtl {
   uint32_t log_cap;     // entries of marked_log
   uint32_t scan_total;  // total of the last scan
   uint32_t exact;       // select through the exact path only
+  uint32_t unmarked;    // points the last decrement took out of the marked set
   uint32_t pad2;
-  uint64_t window;      // candidates: marked points with a priority below this
+  uint64_t arrive;      // round launch: finished workgroups << 40 | marked points they saw
 };
 
 static_assert(offsetof(NbdCtl, done) == offsetof(NbdCtl, round) + 4, "round, done adjacent");
+static_assert(offsetof(NbdCtl, arrive) % 8 == 0, "64-bit arrival counter");
 
 struct NbdCand {
   uint64_t pri;
@@ -95,8 +98,6 @@ struct NbdWs {
   uint2* rng;           // [n * 9] point ranges of the 9 neighbour runs of a cell
   uint32_t* cnt;        // [n] present neighbours
   uint8_t* alive;       // [n]
-  uint8_t* mflag;       // [n] marked in the current round
-  uint32_t* partial;    // [mark workgroups] marked per workgroup
   NbdCand* cand;        // [n]
   uint32_t* del;        // [round_size]
   int64_t* marked_log;  // [log_cap]
@@ -242,12 +243,23 @@ __global__ __launch_bounds__(kNbdBlock) void nbd_ranges_kernel(NbdWs w) {
   }
 }
 
-// Neighbours of every point before any deletion.
+// Wave-aggregated add of a per-lane count (every lane of the wave active).
+__device__ __forceinline__ void nbd_wave_add(uint32_t* ctr, uint32_t v) {
+  const uint32_t tot = wave_incl_add(v);
+  const uint32_t all = (uint32_t)__shfl((int)tot, 63);
+  if ((threadIdx.x & 63) == 63 && all) atomicAdd(ctr, all);
+}
+
+// Neighbours of every point before any deletion, and the first round's marked
+// count.
 __global__ __launch_bounds__(kNbdBlock) void nbd_count_kernel(NbdWs w) {
   const NbdCtl c = *w.ctl;
   if (c.status != kFrameOk) return;
   const uint32_t nth = gridDim.x * blockDim.x;
-  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < c.nv; j += nth) {
+  uint32_t marked = 0;
+  for (uint32_t j0 = blockIdx.x * blockDim.x; j0 < c.nv; j0 += nth) {
+    const uint32_t j = j0 + threadIdx.x;
+    if (j >= c.nv) continue;
     const float px = w.sx[j], py = w.sy[j], pz = w.sz[j];
     const uint2* rg = w.rng + (size_t)w.scell[j] * 9;
     uint32_t cnt = 0;
@@ -260,102 +272,29 @@ __global__ __launch_bounds__(kNbdBlock) void nbd_count_kernel(NbdWs w) {
     }
     w.cnt[j] = cnt;
     w.alive[j] = 1;
+    marked += cnt > c.umbral ? 1u : 0u;
     if (w.count0) w.count0[w.sidx[j]] = cnt;
   }
+  nbd_wave_add(&w.ctl->marked, marked);
 }
 
 // ----------------------------------------------------------- rounds ----
-// Marked points are flagged, and every workgroup writes its count of them.
-__global__ __launch_bounds__(kNbdBlock) void nbd_mark_kernel(NbdWs w) {
-  const NbdCtl c = *w.ctl;
-  if (c.done) return;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {  // the last round's lists are used up
-    w.ctl->ndel = 0u;
-    w.ctl->ncand = 0u;
+// The priority window [0, T) of a round with M marked points: expected to hold
+// the round_size smallest priorities with a margin of 8 standard deviations
+// (priorities are uniform: the count below T is binomial).  T only limits
+// which points are candidates, never which are deleted.
+__device__ __forceinline__ uint64_t nbd_window(uint32_t M, uint32_t K) {
+  uint64_t T = ~0ull;
+  if (M > K) {
+    const double want = (double)K + 8.0 * sqrt((double)K) + 32.0;
+    const double r = want / (double)M;
+    if (r < 1.0) T = (uint64_t)(r * 18446744073709551616.0);
   }
-  const uint32_t nth = gridDim.x * blockDim.x;
-  uint32_t total = 0;
-  for (uint32_t j0 = blockIdx.x * blockDim.x; j0 < c.nv; j0 += nth) {
-    const uint32_t j = j0 + threadIdx.x;
-    bool mk = false;
-    if (j < c.nv) {
-      mk = w.alive[j] && w.cnt[j] > c.umbral;
-      w.mflag[j] = mk ? 1 : 0;
-    }
-    total += (uint32_t)__syncthreads_count(mk);
-  }
-  if (threadIdx.x == 0) w.partial[blockIdx.x] = total;
+  return T;
 }
 
-// One workgroup: the round's marked count; the last round if it is at most
-// round_size; else the priority window [0, T) expected to hold the round_size
-// smallest priorities with a margin of 8 standard deviations (priorities are
-// uniform: the count below T is binomial).  T only limits which points are
-// candidates, never which are deleted.
-__global__ __launch_bounds__(1024) void nbd_select_kernel(NbdWs w, uint32_t nparts) {
-  __shared__ uint32_t ws[1024 / 64];
-  if (w.ctl->done) return;
-  const uint32_t K = w.ctl->round_size;
-  const uint32_t round = w.ctl->round;
-  uint32_t s = 0;
-  for (uint32_t i = threadIdx.x; i < nparts; i += 1024) s += w.partial[i];
-  uint32_t M;
-  (void)block_excl_scan<1024>(s, ws, M);
-  if (threadIdx.x == 0) {
-    if (round < w.ctl->log_cap) w.marked_log[round] = (int64_t)M;
-    w.ctl->marked = M;
-    w.ctl->last = M <= K ? 1u : 0u;
-    uint64_t T = ~0ull;
-    if (M > K) {
-      const double want = (double)K + 8.0 * sqrt((double)K) + 32.0;
-      const double r = want / (double)M;
-      if (r < 1.0) T = (uint64_t)(r * 18446744073709551616.0);
-    }
-    w.ctl->window = T;
-  }
-}
-
-// In the last round every marked point is deleted; otherwise the marked
-// points with a priority below the window become candidates.  Appends are
-// gathered per workgroup (one atomic each).
-__global__ __launch_bounds__(kNbdBlock) void nbd_collect_kernel(NbdWs w) {
-  __shared__ uint32_t ws[kNbdBlock / 64];
-  __shared__ uint32_t base_s;
-  const NbdCtl c = *w.ctl;
-  if (c.done || (!c.last && c.exact)) return;
-  const uint32_t nth = gridDim.x * blockDim.x;
-  for (uint32_t j0 = blockIdx.x * blockDim.x; j0 < c.nv; j0 += nth) {
-    const uint32_t j = j0 + threadIdx.x;
-    bool sel = false;
-    uint64_t pri = 0;
-    if (j < c.nv && w.mflag[j]) {
-      if (c.last) {
-        sel = true;
-      } else {
-        pri = nbd_priority(c, w.sidx[j], c.round);
-        sel = pri < c.window;
-      }
-    }
-    uint32_t tot;
-    const uint32_t off = block_excl_scan<kNbdBlock>(sel ? 1u : 0u, ws, tot);
-    if (tot == 0) continue;
-    if (threadIdx.x == 0) base_s = atomicAdd(c.last ? &w.ctl->ndel : &w.ctl->ncand, tot);
-    __syncthreads();
-    if (sel) {
-      const uint32_t at = base_s + off;
-      if (c.last) {
-        w.del[at] = j;
-        w.alive[j] = 0;
-      } else {
-        NbdCand cd;
-        cd.pri = pri;
-        cd.idx = w.sidx[j];
-        cd.pos = j;
-        w.cand[at] = cd;
-      }
-    }
-    __syncthreads();  // base_s is reused
-  }
+__device__ __forceinline__ bool nbd_marked(const NbdWs& w, uint32_t umbral, uint32_t j) {
+  return w.alive[j] && w.cnt[j] > umbral;
 }
 
 __device__ __forceinline__ bool nbd_key_less(uint64_t pa, uint32_t ia, uint64_t pb, uint32_t ib) {
@@ -366,8 +305,12 @@ constexpr int kPickBlock = 1024;
 constexpr int kPickCap = 4096;   // candidates bucketed in LDS
 constexpr int kPickBins = 4096;  // buckets of the window
 constexpr int kPickEdge = 256;   // candidates of the boundary bucket ranked in LDS
+constexpr int kCollectItems = 2; // points per thread per collect step
 
-// One workgroup: the round_size marked points of smallest (priority, index)
+// The round: every workgroup collects (in the last round every marked point
+// is deleted; otherwise the marked points below the window become
+// candidates, appends gathered per workgroup), and the workgroup that finishes
+// last picks: the round_size marked points of smallest (priority, index)
 // are deleted.  Usually from the window's candidates: they are counted into
 // 4096 buckets by their priority's leading bits (priorities in the window are
 // uniform, so a bucket holds about one); a block scan finds the bucket that
@@ -377,7 +320,7 @@ constexpr int kPickEdge = 256;   // candidates of the boundary bucket ranked in 
 // asked for, a radix select over every marked point, most significant byte
 // first over the 64 priority bits and then the 32 index bits, decides
 // instead.  Keys are distinct (indices are), so exactly round_size go.
-__global__ __launch_bounds__(kPickBlock) void nbd_pick_kernel(NbdWs w) {
+__global__ __launch_bounds__(kPickBlock) void nbd_round_kernel(NbdWs w) {
   __shared__ uint64_t cp[kPickCap];
   __shared__ uint32_t ci[kPickCap];
   __shared__ uint32_t cpos[kPickCap];
@@ -387,23 +330,115 @@ __global__ __launch_bounds__(kPickBlock) void nbd_pick_kernel(NbdWs w) {
   __shared__ uint32_t ws[kPickBlock / 64];
   __shared__ uint32_t h[256];
   __shared__ uint64_t pfx_pri;
-  __shared__ uint32_t pfx_idx, need_s, ndel_s, bnd_s, nedge_s;
+  __shared__ uint32_t pfx_idx, need_s, ndel_s, bnd_s, nedge_s, base_s, picker_s, mtot_s;
   const NbdCtl c = *w.ctl;
   if (c.done) return;
   const uint32_t t = threadIdx.x;
   const uint32_t K = c.round_size;
-  if (!c.last) {
-    const uint32_t nc = c.ncand;
+  const bool surely_last = c.marked <= K;
+  // the window is sized for an estimate of this round's marked count: the
+  // upper bound less twice the points the last decrement unmarked (a window
+  // too narrow falls back to the exact select; one too wide costs LDS work)
+  const uint32_t est = max(max(K + 1u, c.marked / 2u),
+                           c.marked > 2u * c.unmarked ? c.marked - 2u * c.unmarked : 0u);
+  const uint64_t window = nbd_window(est, K);
+
+  // ---- collect, and count the marked points: chunks of kCollectItems *
+  // kPickBlock consecutive points per workgroup, item u of thread t at
+  // u * kPickBlock + t (independent priorities in flight together)
+  uint32_t seen = 0;
+  constexpr uint32_t chunk = kCollectItems * kPickBlock;
+  const uint32_t stride = gridDim.x * chunk;
+  if (surely_last || !c.exact) {
+    for (uint32_t j0 = blockIdx.x * chunk; j0 < c.nv; j0 += stride) {
+      bool sel[kCollectItems];
+      uint64_t pri[kCollectItems];
+#pragma unroll
+      for (int u = 0; u < kCollectItems; ++u) {
+        const uint32_t j = j0 + u * kPickBlock + t;
+        sel[u] = false;
+        pri[u] = 0;
+        if (j < c.nv && nbd_marked(w, c.umbral, j)) {
+          ++seen;
+          if (surely_last) {
+            sel[u] = true;
+          } else {
+            pri[u] = nbd_priority(c, w.sidx[j], c.round);
+            sel[u] = pri[u] < window;
+          }
+        }
+      }
+      uint32_t mine = 0;
+#pragma unroll
+      for (int u = 0; u < kCollectItems; ++u) mine += sel[u] ? 1u : 0u;
+      uint32_t tot;
+      uint32_t at = block_excl_scan<kPickBlock>(mine, ws, tot);
+      if (tot == 0) continue;
+      if (t == 0) base_s = atomicAdd(surely_last ? &w.ctl->ndel : &w.ctl->ncand, tot);
+      __syncthreads();
+      at += base_s;
+#pragma unroll
+      for (int u = 0; u < kCollectItems; ++u) {
+        if (!sel[u]) continue;
+        const uint32_t j = j0 + u * kPickBlock + t;
+        if (surely_last) {
+          w.del[at] = j;
+          w.alive[j] = 0;
+        } else {
+          NbdCand cd;
+          cd.pri = pri[u];
+          cd.idx = w.sidx[j];
+          cd.pos = j;
+          w.cand[at] = cd;
+        }
+        ++at;
+      }
+      __syncthreads();  // base_s is reused
+    }
+  } else {
+    for (uint32_t j = blockIdx.x * kPickBlock + t; j < c.nv; j += gridDim.x * kPickBlock)
+      seen += nbd_marked(w, c.umbral, j) ? 1u : 0u;
+  }
+  uint32_t wg_seen;
+  (void)block_excl_scan<kPickBlock>(seen, ws, wg_seen);
+  // ---- the workgroup that finishes last picks.  Every wave waits for its
+  // appends to reach the L2 of its XCD, then one release per workgroup writes
+  // them back before the workgroup counts itself in (a release in every wave
+  // measured 16 times the write-backs, and 40 us per round); the picker's
+  // acquire drops stale lines before its waves read the lists.  One 64-bit
+  // add counts the workgroup in and adds its marked points.
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (t == 0) {
+    fence_rel();
+    const uint64_t before =
+        atomicAdd((unsigned long long*)&w.ctl->arrive, (1ull << 40) | (uint64_t)wg_seen);
+    picker_s = (uint32_t)(before >> 40) == gridDim.x - 1 ? 1u : 0u;
+    mtot_s = (uint32_t)(before & ((1ull << 40) - 1ull)) + wg_seen;
+    if (picker_s) fence_acq();
+    ndel_s = 0u;
+  }
+  __syncthreads();
+  if (!picker_s) return;
+  const uint32_t M = mtot_s;  // the round's marked points
+  const bool last = M <= K;
+  if (last && !surely_last) {
+    // every marked point goes (the collect took candidates instead); a point
+    // is tested once, by one thread, before it can be deleted
+    for (uint32_t j = t; j < c.nv; j += kPickBlock) {
+      if (!nbd_marked(w, c.umbral, j)) continue;
+      w.del[atomicAdd(&ndel_s, 1u)] = j;
+      w.alive[j] = 0;
+    }
+  } else if (!last) {
+    const uint32_t nc = ld_rlx(&w.ctl->ncand);
     if (!c.exact && nc >= K && nc <= (uint32_t)kPickCap) {
       // bucket of a priority in [0, window): its leading bits below the
       // window's top bit, 12 of them
-      const int wbits = c.window == ~0ull ? 64 : 64 - __clzll(c.window);
+      const int wbits = window == ~0ull ? 64 : 64 - __clzll(window);
       const int shift = max(0, wbits - 12);
       for (uint32_t k = t; k < (uint32_t)kPickBins; k += kPickBlock) hb[k] = 0u;
-      if (t == 0) {
-        ndel_s = 0u;
-        nedge_s = 0u;
-      }
+      if (t == 0) nedge_s = 0u;
       __syncthreads();
       for (uint32_t k = t; k < nc; k += kPickBlock) {
         const NbdCand cd = w.cand[k];
@@ -476,14 +511,12 @@ __global__ __launch_bounds__(kPickBlock) void nbd_pick_kernel(NbdWs w) {
         }
       }
       __syncthreads();
-      if (t == 0) w.ctl->ndel = ndel_s;
     } else {
       // exact path over every marked point
       if (t == 0) {
         pfx_pri = 0ull;
         pfx_idx = 0u;
         need_s = K;
-        ndel_s = 0u;
       }
       __syncthreads();
       for (int level = 0; level < 12; ++level) {
@@ -496,7 +529,7 @@ __global__ __launch_bounds__(kPickBlock) void nbd_pick_kernel(NbdWs w) {
         const uint64_t pp = pfx_pri;
         const uint32_t pi = pfx_idx;
         for (uint32_t j = t; j < c.nv; j += kPickBlock) {
-          if (!w.mflag[j]) continue;
+          if (!nbd_marked(w, c.umbral, j)) continue;
           const uint32_t idx = w.sidx[j];
           const uint64_t pri = nbd_priority(c, idx, c.round);
           if ((pri & pmask) != pp || (idx & imask) != pi) continue;
@@ -519,8 +552,9 @@ __global__ __launch_bounds__(kPickBlock) void nbd_pick_kernel(NbdWs w) {
       }
       const uint64_t tp = pfx_pri;
       const uint32_t ti = pfx_idx;
+      // (a point is tested once, by one thread, before it can be deleted)
       for (uint32_t j = t; j < c.nv; j += kPickBlock) {
-        if (!w.mflag[j]) continue;
+        if (!nbd_marked(w, c.umbral, j)) continue;
         const uint32_t idx = w.sidx[j];
         const uint64_t pri = nbd_priority(c, idx, c.round);
         if (!nbd_key_less(tp, ti, pri, idx)) {  // key <= the round_size-th smallest
@@ -528,14 +562,20 @@ __global__ __launch_bounds__(kPickBlock) void nbd_pick_kernel(NbdWs w) {
           w.alive[j] = 0;
         }
       }
-      __syncthreads();
-      if (t == 0) w.ctl->ndel = ndel_s;
     }
   }
   __syncthreads();
   if (t == 0) {
+    const uint32_t nd = surely_last ? ld_rlx(&w.ctl->ndel) : ndel_s;
+    if (c.round < c.log_cap) w.marked_log[c.round] = (int64_t)M;
+    w.ctl->ndel_out = nd;
+    w.ctl->marked = M - nd;  // counts only fall: at least next round's marked points
+    w.ctl->unmarked = c.marked - M;
+    w.ctl->ndel = 0u;
+    w.ctl->ncand = 0u;
+    w.ctl->arrive = 0ull;
     w.ctl->round = c.round + 1u;
-    if (c.last) w.ctl->done = 1u;
+    if (last) w.ctl->done = 1u;
   }
 }
 
@@ -547,7 +587,8 @@ __global__ __launch_bounds__(kNbdBlock) void nbd_decrement_kernel(NbdWs w) {
   if (c.done) return;
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t waves = gridDim.x * (kNbdBlock / 64);
-  for (uint32_t g = blockIdx.x * (kNbdBlock / 64) + (threadIdx.x >> 6); g < c.ndel; g += waves) {
+  for (uint32_t g = blockIdx.x * (kNbdBlock / 64) + (threadIdx.x >> 6); g < c.ndel_out;
+       g += waves) {
     const uint32_t d = w.del[g];
     const float px = w.sx[d], py = w.sy[d], pz = w.sz[d];
     const uint2* rg = w.rng + (size_t)w.scell[d] * 9;
@@ -560,15 +601,29 @@ __global__ __launch_bounds__(kNbdBlock) void nbd_decrement_kernel(NbdWs w) {
       total += q.y - q.x;
       end[r] = total;
     }
-    for (uint32_t k = lane; k < total; k += 64) {
-      uint32_t q = 0, before = 0;
+    // four list positions per lane at a time: their loads are in flight together
+    for (uint32_t k0 = lane; k0 < total; k0 += 4 * 64) {
+      uint32_t q[4];
+      float qx[4], qy[4], qz[4];
 #pragma unroll
-      for (int r = 0; r < 9; ++r) {
-        if (k >= before && k < end[r]) q = lo[r] + (k - before);
-        before = end[r];
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t k = k0 + 64 * u;
+        uint32_t before = 0;
+        q[u] = d;  // past the list: the deleted point itself, never counted
+#pragma unroll
+        for (int r = 0; r < 9; ++r) {
+          if (k >= before && k < end[r]) q[u] = lo[r] + (k - before);
+          before = end[r];
+        }
+        qx[u] = w.sx[q[u]];
+        qy[u] = w.sy[q[u]];
+        qz[u] = w.sz[q[u]];
       }
-      const float d2 = nbd_d2(px, py, pz, w.sx[q], w.sy[q], w.sz[q]);
-      if (q != d && d2 <= c.r2) atomicSub(&w.cnt[q], 1u);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float d2 = nbd_d2(px, py, pz, qx[u], qy[u], qz[u]);
+        if (q[u] != d && d2 <= c.r2) atomicSub(&w.cnt[q[u]], 1u);
+      }
     }
   }
 }

@@ -861,10 +861,12 @@ __device__ __forceinline__ void hist_batch(const Ws& ws, const GIo& io, typename
 
 // End of a histogram tile: the LDS counts go to the frame's histograms (and
 // are cleared for the next tile), then the done counters.
+// `call_counters`: also the call-wide counters (a streaming launch adds its
+// workgroup's totals to them once, at its end).
 template <class C>
 __device__ __forceinline__ void hist_finish(const Ws& ws, typename C::HistSmem& hs, int b,
                                             const FrameParams& f, bool persistent,
-                                            uint32_t tiles = 1u) {
+                                            uint32_t tiles = 1u, bool call_counters = true) {
   const int P = f.status == kFrameOverflow ? 0 : f.passes;
   __syncthreads();
   for (int i = threadIdx.x; i < P * C::R; i += C::BLOCK) {
@@ -877,10 +879,10 @@ __device__ __forceinline__ void hist_finish(const Ws& ws, typename C::HistSmem& 
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    if (P > 0) atomicMax(&ws.ctl->max_passes, (uint32_t)P);
+    if (P > 0 && call_counters) atomicMax(&ws.ctl->max_passes, (uint32_t)P);
     if (persistent) fence_rel();
     atomicAdd(&ws.fs[b].hist_done, tiles);
-    atomicAdd(&ws.ctl->hist_tiles_done, tiles);
+    if (call_counters) atomicAdd(&ws.ctl->hist_tiles_done, tiles);
   }
 }
 
@@ -942,6 +944,7 @@ __device__ void stream_big_tiles(const Ws& ws, const GIo& io, const CallHdr& hdr
   int t = blockIdx.x;
   if (t >= NT) return;
   uint32_t ntl = 0;  // tiles accumulated since the last hand-over
+  uint32_t nall = 0, pmax = 0;  // the workgroup's tiles and largest pass count (histogram)
   int b = frame_of(t);
   int64_t t0 = (int64_t)(t - (int)__builtin_amdgcn_readfirstlane(bc.tp[0][b])) * C::TB;
   int64_t off = wave_uniform(bc.fda[b].off), fn = wave_uniform(bc.fda[b].n);
@@ -996,7 +999,9 @@ __device__ void stream_big_tiles(const Ws& ws, const GIo& io, const CallHdr& hdr
         }
       } else {
         if (hand_over) {
-          hist_finish<C>(ws, sm.hist, b, f, false, ntl);
+          hist_finish<C>(ws, sm.hist, b, f, false, ntl, false);
+          nall += ntl;
+          if (f.status != kFrameOverflow) pmax = max(pmax, (uint32_t)f.passes);
           ntl = 0;
         }
         if (t2 < NT) {
@@ -1004,7 +1009,15 @@ __device__ void stream_big_tiles(const Ws& ws, const GIo& io, const CallHdr& hdr
           hist_start<C>(ws, bc.fda[b2], (int)(t02 / C::TB), f);
         }
       }
-      if (t2 >= NT) break;
+      if (t2 >= NT) {
+        if constexpr (KIND == kHist) {
+          if (threadIdx.x == 0) {
+            if (pmax > 0) atomicMax(&ws.ctl->max_passes, pmax);
+            atomicAdd(&ws.ctl->hist_tiles_done, nall);
+          }
+        }
+        break;
+      }
     }
     cur = nxt;
     t = t2;
