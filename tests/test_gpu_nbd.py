@@ -108,6 +108,20 @@ def test_coincident_cluster_many_rounds():
     check(g, o, x, y, z, None, "cluster")
 
 
+def test_last_round_below_the_bound():
+    """Two coincident clusters: the first round's deletions unmark the smaller
+    cluster at once, so the second round holds fewer than round_size marked
+    points although the bound carried over from the first round (its count
+    less its deletions) is above round_size: that round deletes every marked
+    point and is the last."""
+    p = np.concatenate([np.full((1500, 3), 0.25, np.float32), np.full((600, 3), 5.25, np.float32)])
+    x, y, z = p[:, 0].copy(), p[:, 1].copy(), p[:, 2].copy()
+    print("case nbd two clusters 1500 + 600 umbral 550 round 1000", flush=True)
+    g, o = run_both(x, y, z, None, 0.5, 0.5, 550, 5, 1000)
+    assert list(o["marked"]) == [2100, 773] and o["rounds"] == 2
+    check(g, o, x, y, z, None, "two clusters")
+
+
 def test_edge_cases():
     e = np.zeros(0, np.float32)
     d = to_dev(e, e, e)
