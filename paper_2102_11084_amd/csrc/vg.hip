@@ -862,8 +862,9 @@ vg_status vg_nbd_decimate(const vg_points* p, int64_t n, const vg_nbd_params* pr
     hipLaunchKernelGGL(nbd_ranges_kernel, dim3(gp), dim3(kNbdBlock), 0, s, w);
     hipLaunchKernelGGL(nbd_count_kernel, dim3(gp), dim3(kNbdBlock), 0, s, w);
     // 3. rounds, enqueued in batches ahead of the host's look at the done flag
-    //    (the round kernel's LDS allows one workgroup per CU)
-    const int gr = grid_for(n, kPickBlock, cus);
+    //    (the round kernel's LDS allows one workgroup per CU; a workgroup
+    //    collects kCollectItems * kPickBlock points per step)
+    const int gr = grid_for(n, kCollectItems * kPickBlock, cus);
     const int gd = grid_for(std::min<int64_t>(prm->round_size, n), kNbdBlock / 64, 2048);
     const int64_t max_rounds = n / prm->round_size + 2;
     int64_t issued = 0;
