@@ -1906,6 +1906,12 @@ __global__ __launch_bounds__(C::BLOCK, (kMinWaves<C, KIND>)) void vg_pipeline_ke
   const CallHdr hdr = *ws.hdr;
   const GIo io = global_view(*ws.io);
   const bool persistent = (ph_lo == 0 && ph_hi == C::NPH);
+  // a launch of several radix passes holds only the passes some frame needs
+  // (the histogram launch before it has set max_passes): when that is one
+  // pass, it runs as a one-pass launch, with its own tile order and the fast
+  // dispatch
+  if (!persistent && ph_lo >= C::PH_SORT0 && ph_hi <= C::PH_RED && ph_hi - ph_lo > 1)
+    ph_hi = max(ph_lo + 1, min(ph_hi, C::PH_SORT0 + (int)ld_rlx(&ws.ctl->max_passes)));
   const bool multi = ph_hi - ph_lo > 1;  // several phases: tiles wait on earlier phases
   // a launch of radix passes that no frame needs ends at once (the histogram
   // launch before it has set max_passes)
