@@ -253,3 +253,20 @@ def test_many_frames_match_per_frame_oracle(B):
     x, y, z, rgb, offs, leaves = many_frames(B, seed=B)
     g = run_batched(x, y, z, rgb, offs, leaves)
     check_against_oracle(g, x, y, z, rgb, offs, leaves)
+
+
+def test_frames_longer_than_a_round_of_tiles():
+    """Two frames of more than 4.2 M points (more big tiles than one launch has
+    workgroups, so a workgroup takes several tiles of one frame in a row and
+    accumulates them together) between small frames: every frame against the
+    oracle."""
+    print("case batch with two frames of 5.0 M and 4.6 M points", flush=True)
+    parts = [dg.uniform_cloud(5_000_000, seed=71, side=6.0), dg.rgbd_frame(160, 120, seed=72),
+             dg.uniform_cloud(4_600_000, seed=73, side=3.0), dg.rgbd_frame(64, 48, seed=74)]
+    leaves = np.array([0.05, 0.02, 0.02, 0.1], np.float32)
+    offs = np.zeros(len(parts) + 1, np.int64)
+    offs[1:] = np.cumsum([p[0].size for p in parts])
+    x, y, z, rgb = (np.concatenate([p[a] for p in parts]) for a in range(4))
+    g = run_batched(x, y, z, rgb, offs, leaves)
+    check_against_oracle(g, x, y, z, rgb, offs, leaves)
+
