@@ -724,8 +724,8 @@ NbdLayout make_nbd_layout(size_t o, int64_t n, int64_t round_size) {
 }
 
 struct NbdReadback {
-  uint32_t round, done;  // the same order as in NbdCtl: copied together
-  uint32_t nkeep, pad;
+  uint32_t round, done, marked;  // the same order as in NbdCtl: copied together
+  uint32_t nkeep;
   int32_t status;
 };
 
@@ -866,16 +866,20 @@ vg_status vg_nbd_decimate(const vg_points* p, int64_t n, const vg_nbd_params* pr
     //    collects kCollectItems * kPickBlock points per step)
     const int gr = grid_for(n, kCollectItems * kPickBlock, cus);
     const int gd = grid_for(std::min<int64_t>(prm->round_size, n), kNbdBlock / 64, 2048);
+    // every round but the last deletes round_size marked points, so a round
+    // count of marked / round_size + 1 is enough for what is left: the next
+    // batch holds that many (at most 64), and few launches run after the last
+    // round
     const int64_t max_rounds = n / prm->round_size + 2;
     int64_t issued = 0;
-    int batch = 4;
+    int batch = 8;
     for (;;) {
       for (int r = 0; r < batch; ++r) {
         hipLaunchKernelGGL(nbd_round_kernel, dim3(gr), dim3(kPickBlock), 0, s, w);
         hipLaunchKernelGGL(nbd_decrement_kernel, dim3(gd), dim3(kNbdBlock), 0, s, w);
       }
       issued += batch;
-      if (hipMemcpyAsync(&rb->round, &w.ctl->round, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost,
+      if (hipMemcpyAsync(&rb->round, &w.ctl->round, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost,
                          s) != hipSuccess ||
           hipStreamSynchronize(s) != hipSuccess) {
         rc = VG_ERR_DEVICE;
@@ -886,7 +890,7 @@ vg_status vg_nbd_decimate(const vg_points* p, int64_t n, const vg_nbd_params* pr
         rc = VG_ERR_DEVICE;
         break;
       }
-      batch = std::min(batch * 2, 64);
+      batch = (int)std::min<int64_t>(64, (int64_t)rb->marked / prm->round_size + 1);
     }
   }
   if (rc == VG_OK) {

@@ -68,7 +68,9 @@ struct NbdCtl {
   uint64_t arrive;      // round launch: finished workgroups << 40 | marked points they saw
 };
 
-static_assert(offsetof(NbdCtl, done) == offsetof(NbdCtl, round) + 4, "round, done adjacent");
+static_assert(offsetof(NbdCtl, done) == offsetof(NbdCtl, round) + 4 &&
+                  offsetof(NbdCtl, marked) == offsetof(NbdCtl, round) + 8,
+              "round, done, marked adjacent (read back together)");
 static_assert(offsetof(NbdCtl, arrive) % 8 == 0, "64-bit arrival counter");
 
 struct NbdCand {
