@@ -1284,7 +1284,8 @@ struct vg_map {
   MapWs ws;
   void* mem;
   int64_t cap;
-  uint32_t* host;  // pinned readback
+  uint32_t* host;    // pinned readback
+  uint32_t seq[4];   // operations so far of each counting kind: mark, clear, expire, export
 };
 
 namespace {
@@ -1303,6 +1304,16 @@ bool frustum_ok(const vg_frustum* f) {
     if (!std::isfinite(x)) return false;
   return f->width >= 1 && f->height >= 1 && f->z_near <= f->z_far;
 }
+
+// Counting kinds (vg_map::seq) and their counter pairs in MapCtl.
+enum { kMapMark = 0, kMapClear = 1, kMapExpire = 2, kMapExport = 3 };
+
+// Slot of the next operation of a kind (and count it).
+uint32_t map_next_slot(vg_map* m, int kind) { return m->seq[kind]++ & 1u; }
+
+// Slot the last operation of a kind counted into (slot 1 before the first,
+// which is zero from creation).
+uint32_t map_last_slot(const vg_map* m, int kind) { return (m->seq[kind] + 1u) & 1u; }
 
 // Sync read of n counters of the map's control block (from index i0).
 vg_status map_read(vg_map* m, int i0, int n, hipStream_t s) {
@@ -1372,10 +1383,10 @@ vg_status vg_map_mark(vg_map* m, const float* x, const float* y, const float* z,
   if (!m || n < 0 || stamp == 0) return VG_ERR_ARG;
   if (n > 0 && (!x || !y || !z)) return VG_ERR_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipLaunchKernelGGL(vg_map_zero_kernel, dim3(1), dim3(64), 0, s, &m->ws.ctl->skipped);
-  if (n > 0)
-    hipLaunchKernelGGL(vg_map_mark_kernel, dim3(map_grid((uint64_t)n)), dim3(kMapBlock), 0, s,
-                       m->ws, x, y, z, n, stamp);
+  // an empty mark still runs (one thread block) so that it counts 0 skipped
+  const uint32_t slot = map_next_slot(m, kMapMark);
+  hipLaunchKernelGGL(vg_map_mark_kernel, dim3(map_grid((uint64_t)std::max<int64_t>(n, 1))),
+                     dim3(kMapBlock), 0, s, m->ws, x, y, z, n, stamp, slot);
   return hipGetLastError() == hipSuccess ? VG_OK : VG_ERR_DEVICE;
 }
 
@@ -1393,18 +1404,16 @@ vg_status vg_map_clear_frustum(vg_map* m, const vg_frustum* f, void* stream) {
   fr.z_near = f->z_near;
   fr.z_far = f->z_far;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipLaunchKernelGGL(vg_map_zero_kernel, dim3(1), dim3(64), 0, s, &m->ws.ctl->cleared);
   hipLaunchKernelGGL(vg_map_clear_kernel, dim3(map_grid((uint64_t)m->cap)), dim3(kMapBlock), 0, s,
-                     m->ws, fr);
+                     m->ws, fr, map_next_slot(m, kMapClear));
   return hipGetLastError() == hipSuccess ? VG_OK : VG_ERR_DEVICE;
 }
 
 vg_status vg_map_expire(vg_map* m, uint32_t min_stamp, void* stream) {
   if (!m) return VG_ERR_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipLaunchKernelGGL(vg_map_zero_kernel, dim3(1), dim3(64), 0, s, &m->ws.ctl->expired);
   hipLaunchKernelGGL(vg_map_expire_kernel, dim3(map_grid((uint64_t)m->cap)), dim3(kMapBlock), 0, s,
-                     m->ws, min_stamp);
+                     m->ws, min_stamp, map_next_slot(m, kMapExpire));
   return hipGetLastError() == hipSuccess ? VG_OK : VG_ERR_DEVICE;
 }
 
@@ -1413,13 +1422,13 @@ vg_status vg_map_export(vg_map* m, uint64_t* keys, uint32_t* stamps, int64_t cap
   if (n) *n = 0;
   if (!m || !n || cap < 0 || (cap > 0 && (!keys || !stamps))) return VG_ERR_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipLaunchKernelGGL(vg_map_zero_kernel, dim3(1), dim3(64), 0, s, &m->ws.ctl->live);
+  const uint32_t slot = map_next_slot(m, kMapExport);
   hipLaunchKernelGGL(vg_map_export_kernel, dim3(map_grid((uint64_t)m->cap)), dim3(kMapBlock), 0, s,
-                     m->ws, keys, stamps, (uint64_t)cap);
+                     m->ws, keys, stamps, (uint64_t)cap, slot);
   if (hipGetLastError() != hipSuccess) return VG_ERR_DEVICE;
-  const vg_status rc = map_read(m, 0, 5, s);
+  const vg_status rc = map_read(m, 0, (int)(offsetof(MapCtl, count) / 4), s);
   if (rc != VG_OK) return rc;
-  *n = m->host[4];
+  *n = m->host[offsetof(MapCtl, live) / 4 + slot];
   return m->host[0] ? VG_ERR_WORKSPACE : VG_OK;
 }
 
@@ -1427,31 +1436,31 @@ vg_status vg_map_compact(vg_map* m, void* stream) {
   if (!m) return VG_ERR_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int g = map_grid((uint64_t)m->cap);
-  hipLaunchKernelGGL(vg_map_zero_kernel, dim3(1), dim3(64), 0, s, &m->ws.ctl->live);
+  const uint32_t slot = map_next_slot(m, kMapExport);
   hipLaunchKernelGGL(vg_map_export_kernel, dim3(g), dim3(kMapBlock), 0, s, m->ws, m->ws.tkeys,
-                     m->ws.tstamps, (uint64_t)m->cap);
+                     m->ws.tstamps, (uint64_t)m->cap, slot);
   hipLaunchKernelGGL(vg_map_reset_kernel, dim3(g), dim3(kMapBlock), 0, s, m->ws);
-  hipLaunchKernelGGL(vg_map_reinsert_kernel, dim3(g), dim3(kMapBlock), 0, s, m->ws);
+  hipLaunchKernelGGL(vg_map_reinsert_kernel, dim3(g), dim3(kMapBlock), 0, s, m->ws, slot);
   return hipGetLastError() == hipSuccess ? VG_OK : VG_ERR_DEVICE;
 }
 
 vg_status vg_map_stats(vg_map* m, vg_map_info* info, void* stream) {
   if (!m || !info) return VG_ERR_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipLaunchKernelGGL(vg_map_zero_kernel, dim3(1), dim3(64), 0, s, &m->ws.ctl->count[0]);
-  hipLaunchKernelGGL(vg_map_zero_kernel, dim3(1), dim3(64), 0, s, &m->ws.ctl->count[1]);
+  hipLaunchKernelGGL(vg_map_zero2_kernel, dim3(1), dim3(64), 0, s, m->ws.ctl->count);
   hipLaunchKernelGGL(vg_map_count_kernel, dim3(map_grid((uint64_t)m->cap)), dim3(kMapBlock), 0, s,
                      m->ws, m->ws.ctl->count);
   if (hipGetLastError() != hipSuccess) return VG_ERR_DEVICE;
-  const vg_status rc = map_read(m, 0, 7, s);
+  const vg_status rc = map_read(m, 0, (int)(offsetof(MapCtl, pad) / 4), s);
   if (rc != VG_OK) return rc;
+  const uint32_t* h = m->host;
   info->capacity = m->cap;
-  info->occupied = m->host[5];
-  info->used_slots = m->host[6];
-  info->last_skipped = m->host[1];
-  info->last_cleared = m->host[2];
-  info->last_expired = m->host[3];
-  info->full = m->host[0] ? 1 : 0;
+  info->occupied = h[offsetof(MapCtl, count) / 4];
+  info->used_slots = h[offsetof(MapCtl, count) / 4 + 1];
+  info->last_skipped = h[offsetof(MapCtl, skipped) / 4 + map_last_slot(m, kMapMark)];
+  info->last_cleared = h[offsetof(MapCtl, cleared) / 4 + map_last_slot(m, kMapClear)];
+  info->last_expired = h[offsetof(MapCtl, expired) / 4 + map_last_slot(m, kMapExpire)];
+  info->full = h[0] ? 1 : 0;
   return VG_OK;
 }
 

@@ -28,15 +28,25 @@ constexpr int32_t kMapHalfRange = 1 << 20;
 constexpr uint32_t kMapMaxProbe = 4096;  // longer probes report the table as full
 constexpr int kMapBlock = 256;
 
+// Counters of an operation come in pairs: the k-th operation of a kind counts
+// into slot k & 1 and clears slot (k + 1) & 1 for the next one (operations on
+// a map run in stream order), so no launch is spent clearing counters.
 struct MapCtl {
-  uint32_t error;      // non-zero: a probe ran past kMapMaxProbe (table too full)
-  uint32_t skipped;    // points of the last mark outside the key range or not finite
-  uint32_t cleared;    // voxels freed by the last clear
-  uint32_t expired;    // voxels freed by the last expire
-  uint32_t live;       // voxels appended by the last export / compact
-  uint32_t count[2];   // occupied voxels, used slots (stats)
-  uint32_t pad[9];
+  uint32_t error;       // non-zero: a probe ran past kMapMaxProbe (table too full)
+  uint32_t skipped[2];  // points of a mark outside the key range or not finite
+  uint32_t cleared[2];  // voxels freed by a clear
+  uint32_t expired[2];  // voxels freed by an expire
+  uint32_t live[2];     // voxels appended by an export / compact
+  uint32_t count[2];    // occupied voxels, used slots (stats)
+  uint32_t pad[5];
 };
+
+// The counter pair of an operation: this one's slot, and the next one's
+// cleared by the first thread of the launch.
+__device__ __forceinline__ uint32_t* map_slot(uint32_t* pair, uint32_t slot) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) pair[slot ^ 1u] = 0u;
+  return pair + slot;
+}
 
 struct MapWs {
   uint64_t* keys;      // [cap]
@@ -103,7 +113,9 @@ __device__ __forceinline__ int64_t map_find_or_insert(const MapWs& m, uint64_t k
 
 __global__ __launch_bounds__(kMapBlock) void vg_map_mark_kernel(MapWs m, const float* x,
                                                                  const float* y, const float* z,
-                                                                 int64_t n, uint32_t stamp) {
+                                                                 int64_t n, uint32_t stamp,
+                                                                 uint32_t slot) {
+  uint32_t* skipped = map_slot(m.ctl->skipped, slot);
   const int64_t nth = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < n; i0 += nth) {
     const int64_t i = i0 + threadIdx.x;
@@ -118,7 +130,7 @@ __global__ __launch_bounds__(kMapBlock) void vg_map_mark_kernel(MapWs m, const f
         skip = true;
       }
     }
-    map_count(&m.ctl->skipped, skip);
+    map_count(skipped, skip);
   }
 }
 
@@ -147,7 +159,9 @@ __device__ __forceinline__ bool map_in_frustum(const MapWs& m, const MapFrustum&
          v <= __fsub_rn((float)f.height, 0.5f);
 }
 
-__global__ __launch_bounds__(kMapBlock) void vg_map_clear_kernel(MapWs m, MapFrustum f) {
+__global__ __launch_bounds__(kMapBlock) void vg_map_clear_kernel(MapWs m, MapFrustum f,
+                                                                  uint32_t slot) {
+  uint32_t* cleared = map_slot(m.ctl->cleared, slot);
   const uint64_t cap = m.mask + 1;
   const uint64_t nth = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t h0 = (uint64_t)blockIdx.x * blockDim.x; h0 < cap; h0 += nth) {
@@ -160,11 +174,13 @@ __global__ __launch_bounds__(kMapBlock) void vg_map_clear_kernel(MapWs m, MapFru
         hit = true;
       }
     }
-    map_count(&m.ctl->cleared, hit);
+    map_count(cleared, hit);
   }
 }
 
-__global__ __launch_bounds__(kMapBlock) void vg_map_expire_kernel(MapWs m, uint32_t min_stamp) {
+__global__ __launch_bounds__(kMapBlock) void vg_map_expire_kernel(MapWs m, uint32_t min_stamp,
+                                                                   uint32_t slot) {
+  uint32_t* expired = map_slot(m.ctl->expired, slot);
   const uint64_t cap = m.mask + 1;
   const uint64_t nth = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t h0 = (uint64_t)blockIdx.x * blockDim.x; h0 < cap; h0 += nth) {
@@ -177,17 +193,19 @@ __global__ __launch_bounds__(kMapBlock) void vg_map_expire_kernel(MapWs m, uint3
         hit = true;
       }
     }
-    map_count(&m.ctl->expired, hit);
+    map_count(expired, hit);
   }
 }
 
 // Occupied voxels appended to (okeys, ostamps) (at most cap_out written; the
-// count goes to ctl->live).  Appends are gathered per workgroup.
+// count goes to ctl->live[slot]).  Appends are gathered per workgroup.
 __global__ __launch_bounds__(kMapBlock) void vg_map_export_kernel(MapWs m, uint64_t* okeys,
                                                                    uint32_t* ostamps,
-                                                                   uint64_t cap_out) {
+                                                                   uint64_t cap_out,
+                                                                   uint32_t slot) {
   __shared__ uint32_t ws[kMapBlock / 64];
   __shared__ uint32_t base_s;
+  uint32_t* live_ctr = map_slot(m.ctl->live, slot);
   const uint64_t cap = m.mask + 1;
   const uint64_t nth = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t h0 = (uint64_t)blockIdx.x * blockDim.x; h0 < cap; h0 += nth) {
@@ -202,7 +220,7 @@ __global__ __launch_bounds__(kMapBlock) void vg_map_export_kernel(MapWs m, uint6
     uint32_t tot;
     const uint32_t off = block_excl_scan<kMapBlock>(live ? 1u : 0u, ws, tot);
     if (tot == 0) continue;
-    if (threadIdx.x == 0) base_s = atomicAdd(&m.ctl->live, tot);
+    if (threadIdx.x == 0) base_s = atomicAdd(live_ctr, tot);
     __syncthreads();
     const uint64_t at = (uint64_t)base_s + off;
     if (live && at < cap_out) {
@@ -213,10 +231,10 @@ __global__ __launch_bounds__(kMapBlock) void vg_map_export_kernel(MapWs m, uint6
   }
 }
 
-// Counters are zeroed by their own launch before the operation that counts
-// (a reset inside that operation could land after other workgroups counted).
-__global__ void vg_map_zero_kernel(uint32_t* p) {
-  if (threadIdx.x == 0) *p = 0u;
+// The stats counters are zeroed by their own launch before the count (a reset
+// inside it could land after other workgroups counted).
+__global__ void vg_map_zero2_kernel(uint32_t* p) {
+  if (threadIdx.x < 2) p[threadIdx.x] = 0u;
 }
 
 // Occupied voxels and used slots (stats).
@@ -244,9 +262,9 @@ __global__ __launch_bounds__(kMapBlock) void vg_map_reset_kernel(MapWs m) {
   }
 }
 
-// Re-inserts the exported voxels (tkeys, tstamps; ctl->live of them).
-__global__ __launch_bounds__(kMapBlock) void vg_map_reinsert_kernel(MapWs m) {
-  const uint64_t n = m.ctl->live;
+// Re-inserts the exported voxels (tkeys, tstamps; ctl->live[slot] of them).
+__global__ __launch_bounds__(kMapBlock) void vg_map_reinsert_kernel(MapWs m, uint32_t slot) {
+  const uint64_t n = m.ctl->live[slot];
   const uint64_t nth = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += nth) {
     const int64_t h = map_find_or_insert(m, m.tkeys[i]);

@@ -30,6 +30,7 @@ def test_random_sequence_matches_oracle(res):
     rng = np.random.default_rng(int(res * 1000))
     g = vg.VoxelMap(1 << 20, res)
     o = oracle.VoxelMap(res)
+    last = {"skipped": 0, "cleared": 0, "expired": 0}  # the oracle's count of the last op of each kind
     for step in range(12):
         op = step % 4
         if op in (0, 1):
@@ -39,19 +40,22 @@ def test_random_sequence_matches_oracle(res):
             p[:3] = [[1e9, 0, 0], [-1e9, 1, 1], [0.0, 0.0, -0.0]]   # out of range; signed zero
             x, y, z = p[:, 0].copy(), p[:, 1].copy(), p[:, 2].copy()
             g.mark(*to_dev(x, y, z), step + 1)
-            o.mark(x, y, z, step + 1)
+            last["skipped"] = o.mark(x, y, z, step + 1)
         elif op == 2:
             R, t = dg.camera_pose(int(rng.integers(0, 1 << 30)))
             args = frustum_args(R, t)
             g.clear(vg.make_frustum(*args))
-            o.clear(*args)
+            last["cleared"] = o.clear(*args)
         else:
             g.expire(step - 1)
-            o.expire(step - 1)
+            last["expired"] = o.expire(step - 1)
         torch.cuda.synchronize()
         same(g, o, (res, step))
         info = g.stats()
         assert info.full == 0
+        got = {"skipped": info.last_skipped, "cleared": info.last_cleared,
+               "expired": info.last_expired}
+        assert got == last, (res, step, got, last)
     g.compact()
     torch.cuda.synchronize()
     same(g, o, (res, "compact"))
