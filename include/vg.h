@@ -381,7 +381,10 @@ vg_status vg_nbd_decimate(const vg_points *p, int64_t n, const vg_nbd_params *pr
  * vg_map_compact.  Keep the used slots under about half the capacity: a mark
  * whose probe runs too long is dropped and reported (vg_map_stats().full,
  * and VG_ERR_WORKSPACE from vg_map_export).  mark, clear, expire and compact
- * are asynchronous on `stream`; export and stats wait for it. */
+ * are asynchronous on `stream`; export and stats wait for it.  The operations
+ * on one map must run in order (one stream, or streams ordered by the caller):
+ * each counting operation clears the counter that the next one of its kind
+ * uses, and the table itself is shared. */
 typedef struct vg_map vg_map;
 
 typedef struct vg_frustum {
