@@ -1019,20 +1019,41 @@ struct vg_batch_plan {
   Layout L;
   void* ws_base;
   Ws ws;
-  char* staging;       // pinned
+  // Two staging slots: call k fills slot k & 1 (pinned descriptor block) and
+  // replays that slot's graph, so the host waits only for call k - 2 before
+  // it rewrites the slot, and call k + 1 can be enqueued while call k runs.
+  // Calls share the workspace: each call's stream first waits for the call
+  // before it (on the device).
+  char* staging[2];    // pinned
   float* invs;         // host scratch [max_frames]
   int device;
   int cus;
-  hipEvent_t done;
-  bool pending;
+  hipEvent_t done[2];
+  bool pending[2];
+  uint64_t calls;      // calls so far
   int use_graph;
-  hipGraph_t graph;
-  hipGraphExec_t gexec;
+  hipGraph_t graph[2];
+  hipGraphExec_t gexec[2];
   LaunchTimer* timer;  // non-null while timing is on
   int fail_waits;      // test support: calls start with the time-out flag raised
-  bool graph_sparse;   // the captured graph holds the sparse-cell pass
+  bool graph_sparse[2];  // the slot's captured graph holds the sparse-cell pass
   bool host_input;     // the points of later calls are in mapped host memory
 };
+
+namespace {
+
+// Waits on the host for every call of the plan still in flight.
+vg_status plan_wait_all(vg_batch_plan* P) {
+  for (int k = 0; k < 2; ++k) {
+    if (P->pending[k]) {
+      if (hipEventSynchronize(P->done[k]) != hipSuccess) return VG_ERR_DEVICE;
+      P->pending[k] = false;
+    }
+  }
+  return VG_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -1054,26 +1075,31 @@ vg_status vg_batch_plan_create(int max_frames, int64_t max_total_points, vg_key_
   P->v = v;
   P->L = make_layout(max_total_points, max_frames, *v);
   P->ws_base = nullptr;
-  P->staging = nullptr;
   P->invs = nullptr;
-  P->pending = false;
+  P->calls = 0;
   P->use_graph = 0;
-  P->graph = nullptr;
-  P->gexec = nullptr;
-  P->done = nullptr;
+  for (int k = 0; k < 2; ++k) {
+    P->staging[k] = nullptr;
+    P->pending[k] = false;
+    P->graph[k] = nullptr;
+    P->gexec[k] = nullptr;
+    P->done[k] = nullptr;
+    P->graph_sparse[k] = false;
+  }
   P->timer = nullptr;
   P->fail_waits = 0;
-  P->graph_sparse = false;
   P->host_input = false;
   vg_status rc = VG_OK;
   if (hipGetDevice(&P->device) != hipSuccess) rc = VG_ERR_DEVICE;
   if (rc == VG_OK && (P->cus = device_cus(P->device)) <= 0) rc = VG_ERR_DEVICE;
   if (rc == VG_OK && hipMalloc(&P->ws_base, P->L.total) != hipSuccess) rc = VG_ERR_DEVICE;
-  if (rc == VG_OK && hipHostMalloc(reinterpret_cast<void**>(&P->staging), P->L.staged,
-                                   hipHostMallocDefault) != hipSuccess)
-    rc = VG_ERR_DEVICE;
-  if (rc == VG_OK && hipEventCreateWithFlags(&P->done, hipEventDisableTiming) != hipSuccess)
-    rc = VG_ERR_DEVICE;
+  for (int k = 0; k < 2; ++k) {
+    if (rc == VG_OK && hipHostMalloc(reinterpret_cast<void**>(&P->staging[k]), P->L.staged,
+                                     hipHostMallocDefault) != hipSuccess)
+      rc = VG_ERR_DEVICE;
+    if (rc == VG_OK && hipEventCreateWithFlags(&P->done[k], hipEventDisableTiming) != hipSuccess)
+      rc = VG_ERR_DEVICE;
+  }
   if (rc == VG_OK) {
     P->invs = new (std::nothrow) float[max_frames];
     if (!P->invs) rc = VG_ERR_DEVICE;
@@ -1130,10 +1156,7 @@ vg_status vg_batch_plan_set_fail_waits(vg_batch_plan* plan, int enable) {
 
 vg_status vg_batch_plan_set_timing(vg_batch_plan* plan, int enable) {
   if (!plan) return VG_ERR_ARG;
-  if (plan->pending) {
-    if (hipEventSynchronize(plan->done) != hipSuccess) return VG_ERR_DEVICE;
-    plan->pending = false;
-  }
+  if (plan_wait_all(plan) != VG_OK) return VG_ERR_DEVICE;
   if (!enable) {
     if (plan->timer) {
       plan->timer->release();
@@ -1191,53 +1214,62 @@ vg_status downsample_batch(vg_batch_plan* P, const vg_points* p, const int64_t* 
   for (int b = 0; b < B; ++b)
     if (!leaf_inverse(leaf[b], &P->invs[b])) return VG_ERR_LEAF;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (P->pending) {
-    if (hipEventSynchronize(P->done) != hipSuccess) return VG_ERR_DEVICE;
-    P->pending = false;
+  // timed calls read their launch events after each call: one call at a time
+  const int slot = P->timer ? 0 : (int)(P->calls & 1u);
+  if (P->timer && plan_wait_all(P) != VG_OK) return VG_ERR_DEVICE;
+  if (P->pending[slot]) {
+    if (hipEventSynchronize(P->done[slot]) != hipSuccess) return VG_ERR_DEVICE;
+    P->pending[slot] = false;
   }
+  char* const stg = P->staging[slot];
   CallHdr hdr;
-  if (!fill_staging(P->staging, P->L, *P->v, p, offs, leaf, P->invs, B, out, out_offsets,
+  if (!fill_staging(stg, P->L, *P->v, p, offs, leaf, P->invs, B, out, out_offsets,
                     frame_status, P->key_mode, P->fail_waits, &hdr, P->ws, filters,
                     P->host_input))
     return VG_ERR_ARG;
+  // the call before this one uses the same workspace (on another stream,
+  // perhaps): this call's stream waits for it on the device
+  if (P->pending[slot ^ 1] && hipStreamWaitEvent(s, P->done[slot ^ 1], 0) != hipSuccess)
+    return VG_ERR_DEVICE;
   const bool sparse = (hdr.filt & kFiltMinPts) != 0;
   vg_status rc = VG_OK;
   if (P->use_graph && !P->timer) {
     // the graph holds the sparse-cell pass once a call has needed it (its
     // kernels exit at once for calls that do not)
-    if (P->gexec && sparse && !P->graph_sparse) {
-      (void)hipGraphExecDestroy(P->gexec);
-      (void)hipGraphDestroy(P->graph);
-      P->gexec = nullptr;
-      P->graph = nullptr;
+    if (P->gexec[slot] && sparse && !P->graph_sparse[slot]) {
+      (void)hipGraphExecDestroy(P->gexec[slot]);
+      (void)hipGraphDestroy(P->graph[slot]);
+      P->gexec[slot] = nullptr;
+      P->graph[slot] = nullptr;
     }
-    if (!P->gexec) {
+    if (!P->gexec[slot]) {
       hipStream_t cs;
       if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return VG_ERR_DEVICE;
       if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         (void)hipStreamDestroy(cs);
         return VG_ERR_DEVICE;
       }
-      rc = enqueue(*P->v, P->L, P->ws, P->staging, P->tuning.exec_mode, P->cus,
+      rc = enqueue(*P->v, P->L, P->ws, stg, P->tuning.exec_mode, P->cus,
                    P->tuning.blocks_per_cu, cs, nullptr, sparse);
       hipGraph_t g = nullptr;
       const bool ok = hipStreamEndCapture(cs, &g) == hipSuccess && rc == VG_OK &&
-                      hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0) == hipSuccess;
+                      hipGraphInstantiate(&P->gexec[slot], g, nullptr, nullptr, 0) == hipSuccess;
       (void)hipStreamDestroy(cs);
       if (!ok) {
         if (g) (void)hipGraphDestroy(g);
-        P->gexec = nullptr;
+        P->gexec[slot] = nullptr;
         return VG_ERR_DEVICE;
       }
-      P->graph = g;
-      P->graph_sparse = sparse;
+      P->graph[slot] = g;
+      P->graph_sparse[slot] = sparse;
     }
-    if (hipGraphLaunch(P->gexec, s) != hipSuccess) rc = VG_ERR_DEVICE;
+    if (hipGraphLaunch(P->gexec[slot], s) != hipSuccess) rc = VG_ERR_DEVICE;
   } else {
-    rc = enqueue(*P->v, P->L, P->ws, P->staging, P->tuning.exec_mode, P->cus,
+    rc = enqueue(*P->v, P->L, P->ws, stg, P->tuning.exec_mode, P->cus,
                  P->tuning.blocks_per_cu, s, P->timer, sparse);
   }
-  if (hipEventRecord(P->done, s) == hipSuccess) P->pending = true;
+  if (hipEventRecord(P->done[slot], s) == hipSuccess) P->pending[slot] = true;
+  ++P->calls;
   return rc;
 }
 
@@ -1262,15 +1294,18 @@ vg_status vg_downsample_batched_filtered(vg_batch_plan* P, const vg_points* p,
 
 vg_status vg_batch_plan_destroy(vg_batch_plan* P) {
   if (!P) return VG_ERR_ARG;
-  if (P->pending && P->done) (void)hipEventSynchronize(P->done);
-  if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
-  if (P->graph) (void)hipGraphDestroy(P->graph);
-  if (P->done) (void)hipEventDestroy(P->done);
+  for (int k = 0; k < 2; ++k)
+    if (P->pending[k] && P->done[k]) (void)hipEventSynchronize(P->done[k]);
+  for (int k = 0; k < 2; ++k) {
+    if (P->gexec[k]) (void)hipGraphExecDestroy(P->gexec[k]);
+    if (P->graph[k]) (void)hipGraphDestroy(P->graph[k]);
+    if (P->done[k]) (void)hipEventDestroy(P->done[k]);
+    if (P->staging[k]) (void)hipHostFree(P->staging[k]);
+  }
   if (P->timer) {
     P->timer->release();
     delete P->timer;
   }
-  if (P->staging) (void)hipHostFree(P->staging);
   if (P->ws_base) (void)hipFree(P->ws_base);
   delete[] P->invs;
   delete P;

@@ -270,3 +270,28 @@ def test_frames_longer_than_a_round_of_tiles():
     g = run_batched(x, y, z, rgb, offs, leaves)
     check_against_oracle(g, x, y, z, rgb, offs, leaves)
 
+
+@pytest.mark.parametrize("use_graph", [False, True])
+@pytest.mark.parametrize("two_streams", [False, True])
+def test_back_to_back_calls_without_sync(use_graph, two_streams):
+    """Four calls of one plan on different batches, enqueued without waiting in
+    between (the plan waits only for the call two back before it rewrites a
+    staging slot), on one stream or alternating between two: every call's
+    outputs against the oracle."""
+    print(f"case back-to-back calls, graph {use_graph}, two streams {two_streams}", flush=True)
+    batches = [small_batch(seed=s) for s in (10, 11, 12, 13)]
+    B = len(batches[0][5])
+    n_max = max(b[0].size for b in batches)
+    devs = [to_dev(b[0], b[1], b[2], b[3].reshape(-1)) for b in batches]
+    torch.cuda.synchronize()
+    plan = vg.BatchPlan(B, n_max, vg.KEY_LINEAR, None, use_graph=use_graph)
+    streams = [torch.cuda.current_stream()] + ([torch.cuda.Stream()] if two_streams else [])
+    outs = []
+    for i, (b, dv) in enumerate(zip(batches, devs)):
+        with torch.cuda.stream(streams[i % len(streams)]):
+            outs.append(plan.run(*dv, b[4], b[5]))
+    torch.cuda.synchronize()
+    plan.close()
+    for b, o in zip(batches, outs):
+        check_against_oracle(host(o), *b)
+
