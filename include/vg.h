@@ -193,8 +193,11 @@ vg_status vg_batch_plan_set_graph(vg_batch_plan *plan, int use_graph);
  *   VG_OK, VG_ERR_GRID_OVERFLOW (that frame has no rows), or VG_ERR_DEVICE in
  *   every frame when a device-side wait of the call timed out (then every
  *   output of the call, out_offsets included, is unspecified).
- * Fully asynchronous on `stream`; a later call on the same plan waits for
- * the earlier one's descriptor copy before reusing the pinned buffer.
+ * Fully asynchronous on `stream`.  A plan has two pinned descriptor slots,
+ * used in turn: a call waits on the host only for the call two before it
+ * (whose slot it reuses), and its stream waits on the device for the call
+ * just before it (calls of a plan share its workspace and run one after the
+ * other, whichever streams they come on).
  * Host-side errors (VG_ERR_ARG, VG_ERR_LEAF) are returned before anything is
  * enqueued. */
 vg_status vg_downsample_batched(vg_batch_plan *plan, const vg_points *p,
