@@ -517,7 +517,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (frames shard across GPUs by design, "
+        print("bench.py: libvg runs on one GPU here (frames would shard across GPUs by frame, "
               "but no multi-GPU path is built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
